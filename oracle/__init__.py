@@ -1,0 +1,227 @@
+"""CPU FP64 oracle for the Deformable Beta Splatting rasterizer.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py``.  The product package never imports
+it, and it imports nothing from the product package.
+
+The arithmetic lives in ``dbs_oracle.c`` (plain C, double precision, OpenMP
+over pixels); this module only marshals numpy arrays.  Scenes and cameras
+are the plain dicts described in ``paper_2501_18630_amd.scenes`` (float32
+values are widened exactly to float64 here).
+
+Functions and the passage each follows:
+  beta_kernel ...... Sec. 3.1, Eqs. (2)-(3)
+  quat_to_rot ...... Sec. 3.2 (R from the quaternion q of Eq. 4)
+  project .......... Sec. 3.2 (Sigma, Sigma' = J W Sigma W^T J^T, mu'), Sec. 3.3 Eq. (8)
+  render ........... Sec. 3.2, Eqs. (5)-(6)
+  render_bwd ....... exact reverse mode of `render`
+  bin_pairs ........ tile binning + (depth, id) order of the splats overlapping each tile
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dbs_oracle.c")
+# ORACLE_LIB_OVERRIDE lets tests/test_oracle_mutants.py point the pins at a
+# scratch build with a planted mistake.
+_LIB = os.environ.get("ORACLE_LIB_OVERRIDE") or os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+PARAMS = ("means", "scales", "quats", "opacities", "betas", "diffuse",
+          "lobe_angles", "lobe_colors", "lobe_betas")
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Camera(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("width", C.c_int32), ("height", C.c_int32),
+                ("near_plane", C.c_double), ("bg", C.c_double * 3)]
+
+
+class _Splats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int32)] + [(k, C.c_void_p) for k in PARAMS]
+
+
+class _Grads(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in PARAMS]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        lib.ob_beta_kernel.restype = C.c_double
+        lib.ob_beta_kernel.argtypes = [C.c_double, C.c_double]
+        lib.ob_quat_to_rot.argtypes = [P, P]
+        lib.ob_project.argtypes = [P, P] + [P] * 10
+        lib.ob_render.argtypes = [P, P, C.c_double, C.c_double, C.c_int64, P, P, P, P, P, P]
+        lib.ob_render_bwd.argtypes = [P, P, C.c_double, C.c_double, C.c_int64, P, P, P, P]
+        lib.ob_bin.restype = C.c_int64
+        lib.ob_bin.argtypes = [C.c_int64, P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                               C.c_int64, P, P]
+        lib.ob_bin_tiles.restype = C.c_int64
+        lib.ob_bin_tiles.argtypes = [C.c_int64, P, P, P, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_int64, P, C.c_int64, P, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _scene64(scene: dict) -> dict:
+    return {k: np.ascontiguousarray(scene[k], dtype=np.float64) for k in PARAMS}
+
+
+def _splats(s64: dict) -> _Splats:
+    n = s64["means"].shape[0]
+    m = s64["lobe_betas"].shape[1] if s64["lobe_betas"].ndim == 2 else 0
+    return _Splats(n, m, *[s64[k].ctypes.data for k in PARAMS])
+
+
+def _camera(cam: dict) -> _Camera:
+    vm = np.asarray(cam["viewmat"], np.float64).reshape(3, 4)
+    bg = np.asarray(cam.get("background", (0.0, 0.0, 0.0)), np.float64).reshape(3)
+    return _Camera((C.c_double * 9)(*vm[:, :3].ravel()), (C.c_double * 3)(*vm[:, 3]),
+                   float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"]),
+                   int(cam["width"]), int(cam["height"]), float(cam["near"]),
+                   (C.c_double * 3)(*bg))
+
+
+def beta_kernel(x: float, b: float) -> float:
+    """B(x; b) = (1 - x)^(4 e^b) on [0, 1], zero for x >= 1."""
+    return _load().ob_beta_kernel(float(x), float(b))
+
+
+def quat_to_rot(q) -> np.ndarray:
+    q = np.ascontiguousarray(q, np.float64).reshape(4)
+    R = np.zeros(9)
+    _load().ob_quat_to_rot(_ptr(q), _ptr(R))
+    return R.reshape(3, 3)
+
+
+def project(scene: dict, cam: dict) -> dict:
+    """Per-splat projection for one view (all FP64)."""
+    lib = _load()
+    s64 = _scene64(scene)
+    n = s64["means"].shape[0]
+    out = dict(valid=np.zeros(n, np.int32), tcam=np.zeros((n, 3)), mean2d=np.zeros((n, 2)),
+               cov2d=np.zeros((n, 3)), conic=np.zeros((n, 3)), extent=np.zeros((n, 2)),
+               beta=np.zeros(n), color=np.zeros((n, 3)), depth_key=np.zeros(n, np.uint32),
+               bbox=np.zeros((n, 4), np.int32))
+    sp, cm = _splats(s64), _camera(cam)
+    lib.ob_project(C.byref(sp), C.byref(cm), *[_ptr(out[k]) for k in
+                   ("valid", "tcam", "mean2d", "cov2d", "conic", "extent", "beta", "color",
+                    "depth_key", "bbox")])
+    return out
+
+
+def _pixels(cam: dict, pixels) -> np.ndarray:
+    if pixels is None:
+        yy, xx = np.mgrid[0:int(cam["height"]), 0:int(cam["width"])]
+        pixels = np.stack([xx.ravel(), yy.ravel()], axis=1)
+    return np.ascontiguousarray(pixels, np.int32).reshape(-1, 2)
+
+
+def crop_pixels(x0: int, y0: int, w: int, h: int) -> np.ndarray:
+    """Row-major pixel list (x, y) of the rectangle [x0, x0+w) x [y0, y0+h)."""
+    yy, xx = np.mgrid[y0:y0 + h, x0:x0 + w]
+    return np.stack([xx.ravel(), yy.ravel()], axis=1).astype(np.int32)
+
+
+def render(scene: dict, cam: dict, alpha_max: float, t_eps: float, pixels=None) -> dict:
+    """Brute-force front-to-back compositing of the listed pixels (x, y);
+    all pixels of the view, row-major, when `pixels` is None."""
+    lib = _load()
+    px = _pixels(cam, pixels)
+    npix = px.shape[0]
+    s64 = _scene64(scene)
+    out = dict(rgb=np.zeros((npix, 3)), T=np.zeros(npix), T_prev=np.zeros(npix),
+               last=np.zeros(npix, np.int64), nsteps=np.zeros(npix, np.int64))
+    sp, cm = _splats(s64), _camera(cam)
+    rc = lib.ob_render(C.byref(sp), C.byref(cm), float(alpha_max), float(t_eps), npix, _ptr(px),
+                       _ptr(out["rgb"]), _ptr(out["T"]), _ptr(out["T_prev"]), _ptr(out["last"]),
+                       _ptr(out["nsteps"]))
+    if rc != 0:
+        raise MemoryError("oracle render failed")
+    return out
+
+
+def render_bwd(scene: dict, cam: dict, alpha_max: float, t_eps: float, dL_drgb, pixels=None,
+               want_abs: bool = False):
+    """Gradient of sum_p dL_drgb[p] . rgb[p] w.r.t. every splat parameter.
+    Returns (grads, abs_sums or None); abs_sums[k] is, per parameter, the sum
+    over pixels of |that pixel's contribution|."""
+    lib = _load()
+    px = _pixels(cam, pixels)
+    g_in = np.ascontiguousarray(dL_drgb, np.float64).reshape(px.shape[0], 3)
+    s64 = _scene64(scene)
+    grads = {k: np.zeros_like(s64[k]) for k in PARAMS}
+    absd = {k: np.zeros_like(s64[k]) for k in PARAMS} if want_abs else None
+    sp, cm = _splats(s64), _camera(cam)
+    gs = _Grads(*[grads[k].ctypes.data for k in PARAMS])
+    ab = _Grads(*[absd[k].ctypes.data for k in PARAMS]) if want_abs else None
+    rc = lib.ob_render_bwd(C.byref(sp), C.byref(cm), float(alpha_max), float(t_eps), px.shape[0],
+                           _ptr(px), _ptr(g_in), C.byref(gs), C.byref(ab) if ab is not None else None)
+    if rc != 0:
+        raise MemoryError("oracle render_bwd failed")
+    return grads, absd
+
+
+def bin_pairs(valid, bbox, depth_key, width: int, height: int, tile_w: int, tile_h: int):
+    """All tiles: (tile_start [n_tiles+1], splat ids in (tile, depth, id) order)."""
+    lib = _load()
+    valid = np.ascontiguousarray(valid, np.int32)
+    bbox = np.ascontiguousarray(bbox, np.int32).reshape(-1, 4)
+    dk = np.ascontiguousarray(depth_key, np.uint32)
+    n = valid.shape[0]
+    n_tiles = ((width + tile_w - 1) // tile_w) * ((height + tile_h - 1) // tile_h)
+    start = np.zeros(n_tiles + 1, np.int64)
+    cap = 1 << 16
+    while True:
+        ids = np.zeros(cap, np.int64)
+        k = lib.ob_bin(n, _ptr(valid), _ptr(bbox), _ptr(dk), width, height, tile_w, tile_h, cap,
+                       _ptr(start), _ptr(ids))
+        if k == -1:
+            raise MemoryError("oracle bin failed")
+        if k >= 0:
+            return start, ids[:k]
+        cap = int(start[-1])
+
+
+def bin_tiles(valid, bbox, depth_key, width: int, tile_w: int, tile_h: int, tiles):
+    """Requested tiles only (brute force per tile): (list_start, ids)."""
+    lib = _load()
+    valid = np.ascontiguousarray(valid, np.int32)
+    bbox = np.ascontiguousarray(bbox, np.int32).reshape(-1, 4)
+    dk = np.ascontiguousarray(depth_key, np.uint32)
+    tiles = np.ascontiguousarray(tiles, np.int64)
+    start = np.zeros(tiles.shape[0] + 1, np.int64)
+    cap = 1 << 16
+    while True:
+        ids = np.zeros(cap, np.int64)
+        k = lib.ob_bin_tiles(valid.shape[0], _ptr(valid), _ptr(bbox), _ptr(dk), width, tile_w,
+                             tile_h, tiles.shape[0], _ptr(tiles), cap, _ptr(start), _ptr(ids))
+        if k == -1:
+            raise MemoryError("oracle bin_tiles failed")
+        if k >= 0:
+            return start, ids[:k]
+        cap = int(start[-1])

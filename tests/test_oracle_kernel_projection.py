@@ -1,0 +1,230 @@
+"""Pins of the oracle's Beta kernel, parameter layout, projection and
+Spherical Beta colour against closed forms, printed numbers and library
+routines (CPU only)."""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.spatial.transform import Rotation
+
+from paper_2501_18630_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_numbers.json")
+
+
+def one_splat(mu, scale, quat=(1, 0, 0, 0), o=0.8, b=0.0, c0=(1, 1, 1), lobes=()):
+    """A scene with a single splat; lobes = [(theta, phi, (r,g,b), b_m), ...]."""
+    m = len(lobes)
+    la = np.array([[l[0], l[1]] for l in lobes], np.float64).reshape(1, m, 2)
+    lc = np.array([l[2] for l in lobes], np.float64).reshape(1, m, 3)
+    lb = np.array([l[3] for l in lobes], np.float64).reshape(1, m)
+    return dict(means=np.array([mu], np.float64), scales=np.array([scale], np.float64),
+                quats=np.array([quat], np.float64), opacities=np.array([o], np.float64),
+                betas=np.array([b], np.float64), diffuse=np.array([c0], np.float64),
+                lobe_angles=la, lobe_colors=lc, lobe_betas=lb)
+
+
+# ---------------------------------------------------------------- kernel (Sec. 3.1)
+
+def test_beta_kernel_boundary_and_range(oracle):
+    # App. A.3 conditions: K(0) = 1, K(1) = 0, K in [0, 1], non-increasing.
+    for b in (-2.0, -0.5, 0.0, 0.7, 2.0):
+        assert oracle.beta_kernel(0.0, b) == 1.0
+        assert oracle.beta_kernel(1.0, b) == 0.0
+        assert oracle.beta_kernel(1.5, b) == 0.0
+        xs = np.linspace(0, 1, 513)
+        v = np.array([oracle.beta_kernel(x, b) for x in xs])
+        assert np.all((v >= 0) & (v <= 1))
+        assert np.all(np.diff(v) <= 0)
+
+
+def test_beta_kernel_integral_closed_form(oracle):
+    # int_0^1 (1-x)^beta dx = 1/(beta+1) with beta = 4 e^b (Eq. 3).
+    for b in (-1.0, -0.3, 0.0, 0.4, 1.2):
+        val, _ = integrate.quad(lambda x: oracle.beta_kernel(x, b), 0.0, 1.0, epsabs=1e-13)
+        assert val == pytest.approx(1.0 / (4.0 * np.exp(b) + 1.0), rel=1e-9)
+
+
+def test_beta_kernel_b0_resembles_gaussian(oracle):
+    # Sec. 3.1: c = 4 makes the b = 0 kernel's integral close to that of exp(-9x/2).
+    g = json.load(open(GOLDEN))["kernel_constant_c"]
+    val, _ = integrate.quad(lambda x: oracle.beta_kernel(x, 0.0), 0.0, 1.0)
+    gauss = (1.0 - np.exp(-g["gaussian_rate"])) / g["gaussian_rate"]
+    assert val == pytest.approx(1.0 / (g["c"] + 1.0), rel=1e-12)
+    assert abs(val - gauss) < 0.02
+    xs = np.linspace(0, 1, 101)
+    dev = max(abs(oracle.beta_kernel(x, 0.0) - np.exp(-g["gaussian_rate"] * x)) for x in xs)
+    assert dev < 0.05
+
+
+# ---------------------------------------------------------------- layout (Sec. 3.3, Tab. ablation)
+
+def test_parameter_layout_matches_printed_memory():
+    """Floats per primitive 15 + 6M reproduce the ratios of the memory
+    column of the ablation table (sb = 1, 2, 4, 6) and the SH3 row (60)."""
+    gold = json.load(open(GOLDEN))
+
+    def floats_per_splat(m):
+        s = scenes.uniform_box_scene(4, [-1, -1, 2], [1, 1, 3], m=m, seed=0)
+        return sum(v[0].size for v in s.values())
+
+    for key in ("memory_tanks_temples_MB", "memory_deep_blending_MB"):
+        col = gold[key]
+        q2 = floats_per_splat(2)
+        for sb, mb in col["sb"].items():
+            assert mb / col["sb"]["2"] == pytest.approx(floats_per_splat(int(sb)) / q2, rel=2e-3)
+        # SH degree 3: 59 geometry+colour floats + b = 60
+        assert col["sh3"] / col["sb"]["2"] == pytest.approx((15 - 3 + 3 * 16) / q2, rel=2e-3)
+    per = gold["sb_feature_dim"]
+    for m in (0, 1, 2, 4):
+        s = scenes.uniform_box_scene(2, [-1, -1, 2], [1, 1, 3], m=m, seed=0)
+        feat = s["diffuse"][0].size + s["lobe_angles"][0].size + s["lobe_colors"][0].size \
+            + s["lobe_betas"][0].size
+        assert feat == per["base"] + per["per_lobe"] * m
+
+
+# ---------------------------------------------------------------- projection (Sec. 3.2)
+
+def test_quat_to_rot_matches_scipy(oracle):
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        q = rng.standard_normal(4) * rng.uniform(0.2, 3.0)
+        R = oracle.quat_to_rot(q)
+        ref = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()  # scipy: (x,y,z,w)
+        np.testing.assert_allclose(R, ref, atol=1e-14)
+
+
+def test_isotropic_on_axis_closed_form(oracle):
+    f, W, H, z, s = 64.0, 64, 64, 4.0, 0.3
+    cam = scenes.camera(W, H, f=f)
+    p = oracle.project(one_splat([0, 0, z], [s, s, s]), cam)
+    R = f * s / z
+    assert p["valid"][0] == 1
+    np.testing.assert_allclose(p["mean2d"][0], [32.0, 32.0], atol=1e-13)
+    np.testing.assert_allclose(p["cov2d"][0], [R * R, 0.0, R * R], rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(p["conic"][0], [1 / R ** 2, 0.0, 1 / R ** 2], rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(p["extent"][0], [R, R], rtol=1e-13)
+    # pixel centres u+0.5 in [32-R, 32+R]
+    lo, hi = int(np.ceil(32 - R - 0.5)), int(np.floor(32 + R - 0.5))
+    np.testing.assert_array_equal(p["bbox"][0], [lo, hi, lo, hi])
+
+
+def test_isotropic_off_axis_affine_jacobian(oracle):
+    # Sigma' = s^2 J J^T = (f s / z)^2 [[1 + x^2/z^2, xy/z^2], [xy/z^2, 1 + y^2/z^2]]
+    f, s = 100.0, 0.2
+    cam = scenes.camera(200, 160, f=f)
+    for (x, y, z) in [(1.0, -0.5, 5.0), (-2.0, 1.5, 3.0), (0.3, 2.2, 7.5)]:
+        p = oracle.project(one_splat([x, y, z], [s, s, s]), cam)
+        k = (f * s / z) ** 2
+        ref = k * np.array([1 + x * x / z / z, x * y / z / z, 1 + y * y / z / z])
+        np.testing.assert_allclose(p["cov2d"][0], ref, rtol=1e-12)
+        np.testing.assert_allclose(p["mean2d"][0], [f * x / z + 100.0, f * y / z + 80.0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.5236, 1.1, -0.7])
+def test_anisotropic_rotation_about_optical_axis(oracle, theta):
+    f, z, sx, sy, sz = 80.0, 5.0, 0.4, 0.1, 0.25
+    cam = scenes.camera(96, 96, f=f)
+    q = [np.cos(theta / 2), 0, 0, np.sin(theta / 2)]
+    p = oracle.project(one_splat([0, 0, z], [sx, sy, sz], quat=q), cam)
+    c, s = np.cos(theta), np.sin(theta)
+    R2 = np.array([[c, -s], [s, c]])
+    ref = (f / z) ** 2 * R2 @ np.diag([sx * sx, sy * sy]) @ R2.T
+    np.testing.assert_allclose(p["cov2d"][0], [ref[0, 0], ref[0, 1], ref[1, 1]], rtol=1e-12, atol=1e-12)
+
+
+def test_rotation_about_x_swaps_y_and_z_scales(oracle):
+    f, z = 80.0, 6.0
+    cam = scenes.camera(96, 96, f=f)
+    q = [np.cos(np.pi / 4), np.sin(np.pi / 4), 0, 0]
+    p = oracle.project(one_splat([0, 0, z], [0.1, 0.2, 0.5], quat=q), cam)
+    np.testing.assert_allclose(p["cov2d"][0], [(f * 0.1 / z) ** 2, 0.0, (f * 0.5 / z) ** 2],
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_camera_pose_and_depth_key(oracle):
+    cam = scenes.look_at_camera([3.0, -4.0, 12.0], 128, 96)
+    p = oracle.project(one_splat([0, 0, 0], [0.1, 0.1, 0.1]), cam)
+    np.testing.assert_allclose(p["mean2d"][0], [64.0, 48.0], atol=1e-5)
+    depth = np.float32(p["tcam"][0, 2])
+    assert p["tcam"][0, 2] == pytest.approx(13.0, rel=1e-6)
+    assert p["depth_key"][0] == depth.view(np.uint32)
+
+
+def test_near_plane_and_degenerate_culling(oracle):
+    cam = scenes.camera(64, 64, f=64.0, near=0.2)
+    s = one_splat([0, 0, 0.2], [0.1] * 3)
+    assert oracle.project(s, cam)["valid"][0] == 0
+    s = one_splat([0, 0, 0.2001], [0.1] * 3)
+    assert oracle.project(s, cam)["valid"][0] == 1
+    s = one_splat([0, 0, -3.0], [0.1] * 3)
+    assert oracle.project(s, cam)["valid"][0] == 0
+    s = one_splat([0, 0, 3.0], [0.0, 0.1, 0.1])        # zero scale along x: det = 0
+    assert oracle.project(s, cam)["valid"][0] == 0
+
+
+def test_extent_is_bounding_box_of_support_ellipse(oracle):
+    rng = np.random.default_rng(3)
+    cam = scenes.camera(128, 128, f=128.0)
+    for _ in range(10):
+        q = rng.standard_normal(4)
+        sc = np.exp(rng.uniform(np.log(0.05), np.log(0.5), 3))
+        p = oracle.project(one_splat([rng.uniform(-1, 1), rng.uniform(-1, 1), 4.0], sc, quat=q), cam)
+        a, b, c = p["cov2d"][0]
+        lam, vec = np.linalg.eigh(np.array([[a, b], [b, c]]))
+        ang = np.linspace(0, 2 * np.pi, 200001)
+        pts = vec @ (np.sqrt(lam)[:, None] * np.stack([np.cos(ang), np.sin(ang)]))
+        np.testing.assert_allclose(p["extent"][0], np.abs(pts).max(axis=1), rtol=1e-8)
+
+
+def test_bbox_is_exactly_the_pixel_centres_inside_the_box(oracle):
+    rng = np.random.default_rng(4)
+    cam = scenes.camera(40, 30, f=40.0)
+    for _ in range(40):
+        mu = [rng.uniform(-0.8, 0.8), rng.uniform(-0.6, 0.6), rng.uniform(1.0, 5.0)]
+        p = oracle.project(one_splat(mu, np.exp(rng.uniform(-4, -1, 3)), quat=rng.standard_normal(4)), cam)
+        (mx, my), (ex, ey) = p["mean2d"][0], p["extent"][0]
+        xs = [u for u in range(40) if mx - ex <= u + 0.5 <= mx + ex]
+        ys = [v for v in range(30) if my - ey <= v + 0.5 <= my + ey]
+        if xs and ys:
+            np.testing.assert_array_equal(p["bbox"][0], [xs[0], xs[-1], ys[0], ys[-1]])
+        else:
+            b = p["bbox"][0]
+            assert b[0] > b[1] or b[2] > b[3]
+
+
+# ---------------------------------------------------------------- Spherical Beta (Sec. 3.3)
+
+def test_spherical_beta_closed_forms(oracle):
+    cam = scenes.camera(64, 64, f=64.0)           # camera at origin looking down +z
+    mu = [0.0, 0.0, 5.0]                          # view direction V = (0, 0, 1)
+    c0, cm = (0.1, 0.2, 0.3), (0.5, 0.25, 0.125)
+    # lobe aligned with V: colour = c0 + c_m
+    p = oracle.project(one_splat(mu, [.1] * 3, c0=c0, lobes=[(0.0, 0.3, cm, 0.4)]), cam)
+    np.testing.assert_allclose(p["color"][0], np.add(c0, cm), atol=1e-14)
+    # lobe perpendicular or opposite: bounded support gives exactly c0
+    for th in (np.pi / 2, 2.0, np.pi):
+        p = oracle.project(one_splat(mu, [.1] * 3, c0=c0, lobes=[(th, 1.0, cm, 0.4)]), cam)
+        np.testing.assert_allclose(p["color"][0], c0, atol=1e-15)
+    # angle gamma: weight cos(gamma)^(4 e^b_m)
+    for gam, bm in ((0.3, 0.0), (1.0, -0.6), (0.7, 0.9)):
+        p = oracle.project(one_splat(mu, [.1] * 3, c0=c0, lobes=[(gam, 2.0, cm, bm)]), cam)
+        w = np.cos(gam) ** (4 * np.exp(bm))
+        np.testing.assert_allclose(p["color"][0], np.add(c0, w * np.asarray(cm)), rtol=1e-12)
+    # no lobes: c0
+    p = oracle.project(one_splat(mu, [.1] * 3, c0=c0), cam)
+    np.testing.assert_allclose(p["color"][0], c0, atol=0)
+
+
+def test_spherical_beta_view_direction_from_camera_to_splat(oracle):
+    # camera at (0,0,-10) (t = (0,0,10)); splat at (6,0,-2): V = normalize((6,0,8)) = (.6, 0, .8)
+    cam = scenes.camera(64, 64, f=64.0, t=[0.0, 0.0, 10.0])
+    th = np.arccos(0.8)
+    p = oracle.project(one_splat([6.0, 0.0, -2.0], [.1] * 3, c0=(0, 0, 0),
+                                 lobes=[(th, 0.0, (1, 1, 1), 0.0)]), cam)
+    np.testing.assert_allclose(p["color"][0], [1, 1, 1], atol=1e-13)
+    p = oracle.project(one_splat([6.0, 0.0, -2.0], [.1] * 3, c0=(0, 0, 0),
+                                 lobes=[(np.pi - th, np.pi, (1, 1, 1), 0.0)]), cam)
+    np.testing.assert_allclose(p["color"][0], [0, 0, 0], atol=1e-15)
