@@ -1,0 +1,224 @@
+/*
+ * dbs.h — C ABI of the MI355X (gfx950) differentiable tile rasterizer for
+ * Deformable Beta Splatting (arXiv 2501.18630).
+ *
+ * The library renders ellipsoidal Beta primitives (Sec. 3.2, Eq. 4) with
+ * Spherical Beta colour (Sec. 3.3, Eq. 8) by depth-ordered front-to-back
+ * compositing (Sec. 3.2, Eq. 6), and differentiates the result with respect
+ * to every primitive parameter.  A render is four calls on one stream:
+ *
+ *   dbs_preprocess   project every (view, splat), Spherical Beta colour,
+ *                    pixel box, tile count, depth key; count visible
+ *                    records and tile pairs
+ *   dbs_bin_sort     list, for every tile of every view, the splats whose
+ *                    box overlaps it, ordered by (depth, splat id)
+ *   dbs_render_fwd   composite every pixel front to back
+ *   dbs_render_bwd   reverse pass: gradients of every splat parameter
+ *
+ * Conventions shared by every call:
+ *   - All pointers are DEVICE pointers unless marked [host].  The caller owns
+ *     all memory; no call allocates, frees or synchronises the device.  Calls
+ *     only enqueue work on `stream` (a hipStream_t; NULL = legacy default
+ *     stream), so a sequence of calls can be captured in a hipGraph.
+ *   - A status is returned synchronously after argument validation and
+ *     launch; DBS_ERR_HIP means a launch failed (hipGetLastError).  Errors
+ *     found on the device (pair capacity exceeded) are reported through a
+ *     device flag, never by aborting.
+ *   - Views are rendered in one batch: view v's image occupies pixels
+ *     [pixel_offset(v), pixel_offset(v) + W_v H_v) of the flat pixel index,
+ *     with pixel_offset(v) = sum_{u<v} W_u H_u.  `image` is planar per view:
+ *     channel c of pixel (x, y) of view v is image[3 pixel_offset(v) +
+ *     c W_v H_v + y W_v + x].  `final_T` and `last_index` hold one value per
+ *     flat pixel.
+ *   - Camera: world->camera x_c = R x_w + t with OpenCV axes (x right, y down,
+ *     z forward); pinhole u = fx x/z + cx, v = fy y/z + cy; the centre of
+ *     pixel (x, y) is (x + 0.5, y + 0.5).  Splats with z <= near_plane, or
+ *     with a non-positive projected-covariance determinant, are culled.
+ *   - Every buffer that `dbs_*_bytes` sizes must stay untouched by the caller
+ *     between the calls that use it.
+ */
+#ifndef DBS_H
+#define DBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DBS_OK = 0,
+    DBS_ERR_INVALID_ARGUMENT = 1, /* null pointer, size out of range, bad camera */
+    DBS_ERR_CAPACITY = 2,         /* a buffer size argument is below what the call needs */
+    DBS_ERR_HIP = 3,              /* a kernel launch failed */
+    DBS_ERR_UNSUPPORTED = 4       /* lobe count, tile shape or batch depth not built */
+} dbs_status;
+
+#define DBS_MAX_LOBES 8
+#define DBS_MAX_VIEWS 1024
+#define DBS_MAX_PAIRS ((int64_t)0x7fffffff)
+
+/* Primitive parameters, Sec. 3.2 Eq. (4) and Sec. 3.3 Eq. (8).  FP32,
+ * row-major, n splats, m Spherical Beta lobes (0..DBS_MAX_LOBES).
+ *   means        [n,3]  centre mu
+ *   scales       [n,3]  s, already activated (> 0)
+ *   quats        [n,4]  q = (w,x,y,z), any non-zero norm; normalised inside
+ *   opacities    [n]    o in [0,1], already activated
+ *   betas        [n]    raw b; the kernel exponent is 4 e^b (Sec. 3.1, Eq. 3)
+ *   diffuse      [n,3]  base colour c0
+ *   lobe_angles  [n,m,2] (theta, phi): R_m = (sin th cos ph, sin th sin ph, cos th)
+ *   lobe_colors  [n,m,3] c_m
+ *   lobe_betas   [n,m]  raw b_m; the lobe exponent is 4 e^{b_m}
+ * Lobe pointers may be NULL when m = 0. */
+typedef struct {
+    const float *means, *scales, *quats, *opacities, *betas, *diffuse;
+    const float *lobe_angles, *lobe_colors, *lobe_betas;
+    int64_t n;
+    int32_t m;
+} dbs_splats;
+
+/* Gradients with the same shapes as dbs_splats, FP32.  dbs_render_bwd ADDS
+ * into them (+=), so gradients accumulate across calls and views; the caller
+ * zeroes them when it wants a fresh gradient. */
+typedef struct {
+    float *means, *scales, *quats, *opacities, *betas, *diffuse;
+    float *lobe_angles, *lobe_colors, *lobe_betas;
+} dbs_splat_grads;
+
+/* [host] One pinhole view. */
+typedef struct {
+    float viewmat[12];     /* row-major 3x4 [R | t], world -> camera */
+    float fx, fy, cx, cy;  /* pixels */
+    int32_t width, height; /* 1..16384 */
+    float near_plane;      /* > 0 */
+    float background[3];   /* fixed background colour, composited with T_final */
+} dbs_camera;
+
+/* Rasterisation settings.  The built tile shapes are 16x16, 16x8, 8x8, 32x8
+ * and 32x16 pixels; batch is the number of splats staged in LDS per step
+ * (64, 128 or 256, and a multiple of tile_w * tile_h or a divisor of it).
+ * A splat contributes alpha = min(alpha_max, o B(r^2; b)) where r^2 < 1; a
+ * pixel stops after the splat that takes its transmittance below t_eps. */
+typedef struct {
+    int32_t tile_w, tile_h;
+    int32_t batch;
+    float t_eps;           /* default 1e-4 */
+    float alpha_max;       /* default 0.99; must lie in (0, 1) */
+    uint32_t flags;        /* DBS_FLAG_* */
+} dbs_raster_cfg;
+
+/* Raster kernels run persistently: a fixed grid drains a device-side queue
+ * of (view, tile) work items ordered heaviest first.  Without this flag one
+ * workgroup is launched per work item. */
+#define DBS_FLAG_PERSISTENT 1u
+
+/* Fills *cfg with the defaults above (16x16 tiles, batch 256, persistent). */
+void dbs_default_cfg(dbs_raster_cfg *cfg);
+
+/* ---- buffer sizes (bytes) ---------------------------------------------- */
+
+/* `projected`: per (view, splat) records plus the view table and counters. */
+size_t dbs_projected_bytes(int64_t n, int32_t n_views);
+
+/* `bins`: sorted tile lists for up to `pair_capacity` (tile, splat) pairs,
+ * tile ranges and the work queue. */
+size_t dbs_bins_bytes(int64_t pair_capacity, const dbs_camera *cams /*[host]*/, int32_t n_views,
+                      const dbs_raster_cfg *cfg /*[host]*/);
+
+/* `workspace`: scratch for dbs_bin_sort and dbs_render_bwd. */
+size_t dbs_workspace_bytes(int64_t n, int32_t n_views, int64_t pair_capacity,
+                           const dbs_camera *cams /*[host]*/, const dbs_raster_cfg *cfg /*[host]*/);
+
+/* ---- the four calls ----------------------------------------------------- */
+
+/* Projection of every (view, splat) record (Sec. 3.2: Sigma = R S S^T R^T,
+ * Sigma' = J W Sigma W^T J^T, mu', conic Sigma'^{-1}, exact support box of
+ * r^2 <= 1) and its Spherical Beta colour (Sec. 3.3, Eq. 8).  Geometry is
+ * evaluated in FP64 and rounded once.  Writes `projected` and, if `counts`
+ * is not NULL, counts[0] = visible records (at least one tile),
+ * counts[1] = (tile, splat) pairs.  cams: [host] n_views cameras. */
+dbs_status dbs_preprocess(const dbs_splats *splats /*[host] struct of device pointers*/,
+                          const dbs_camera *cams /*[host]*/, int32_t n_views,
+                          const dbs_raster_cfg *cfg /*[host]*/,
+                          void *projected, size_t projected_bytes,
+                          int64_t *counts /* device int64[2] or NULL */, void *stream);
+
+/* Tile lists (Sec. 3.2, sorting by depth before Eq. 6): every visible record
+ * is listed in each tile its pixel box overlaps; each list is ordered by the
+ * fp32 bits of the camera-space depth, ties by splat index.  If the number
+ * of pairs exceeds pair_capacity, *overflow (device int32) is set to 1 and
+ * every tile list is left empty; otherwise *overflow is set to 0. */
+dbs_status dbs_bin_sort(const void *projected, const dbs_camera *cams /*[host]*/, int32_t n_views,
+                        const dbs_raster_cfg *cfg /*[host]*/, int64_t n,
+                        int64_t pair_capacity, void *bins, size_t bins_bytes,
+                        void *workspace, size_t workspace_bytes,
+                        int32_t *overflow /* device int32 or NULL */, void *stream);
+
+/* Front-to-back compositing, Sec. 3.2 Eq. (6), of every pixel of every view:
+ *   image      [3 * sum(W H)] FP32, planar per view (see above);
+ *               colour = sum_i c_i alpha_i T_i + T_final * background
+ *   final_T    [sum(W H)] FP32 transmittance after the last processed splat
+ *   last_index [sum(W H)] int32: position in the pair list of the last splat
+ *               with r^2 < 1 that the pixel composited, -1 if none. */
+dbs_status dbs_render_fwd(const void *projected, const void *bins, const dbs_camera *cams /*[host]*/,
+                          int32_t n_views, const dbs_raster_cfg *cfg /*[host]*/, int64_t n,
+                          float *image, float *final_T, int32_t *last_index, void *stream);
+
+/* Reverse pass of dbs_render_fwd and dbs_preprocess: given dL/dimage (same
+ * layout as image) it ADDS dL/dparameter to *grads for every parameter of
+ * Sec. 3.2 Eq. (4) and Sec. 3.3 Eq. (8), including b and b_m through
+ * beta = 4 e^b.  Transmittance is recomputed back to front from final_T and
+ * last_index; a clamped alpha passes no gradient to o, b or the geometry. */
+dbs_status dbs_render_bwd(const dbs_splats *splats /*[host] struct of device pointers*/,
+                          const void *projected, const void *bins,
+                          const dbs_camera *cams /*[host]*/, int32_t n_views,
+                          const dbs_raster_cfg *cfg /*[host]*/,
+                          const float *final_T, const int32_t *last_index, const float *dL_dimage,
+                          dbs_splat_grads *grads /*[host] struct of device pointers*/,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---- loss glue ----------------------------------------------------------- */
+
+/* L1 loss L = scale * sum_k |image_k - target_k| over k < count, and its
+ * gradient dL/dimage_k = scale * sign(image_k - target_k) (sign(0) = 0).
+ * loss (device float, may be NULL) is OVERWRITTEN with L. */
+dbs_status dbs_l1_loss(const float *image, const float *target, int64_t count, float scale,
+                       float *dL_dimage, float *loss, void *stream);
+
+/* ---- introspection (tests, profiling) ------------------------------------ */
+
+/* Device pointers into `projected` for n splats and n_views views:
+ * per record r = v n + i (view-major):
+ *   centre [R] float4 (hi_x, hi_y, lo_x, lo_y): mu' = hi + lo in pixels
+ *   conic  [R] float4 (A00, A01, A11, opacity)
+ *   color  [R] float4 (r, g, b, 4 e^b)
+ *   bbox   [R] int16x4 (x_lo, x_hi, y_lo, y_hi) inclusive pixel box
+ *   depth  [R] uint32 fp32 bits of the camera-space depth
+ *   ntiles [R] uint32 number of tiles the box overlaps (0: culled/empty)
+ *   counts     int64[2] (visible records, pairs)
+ * Any output pointer may be NULL. */
+dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views,
+                                void **centre, void **conic, void **color, void **bbox,
+                                void **depth, void **ntiles, void **counts);
+
+/* Device pointers into `bins`:
+ *   pair_rec   [pair_capacity] uint32 record r = v n + i per pair, sorted
+ *   tile_range [n_tiles] uint32x2 (start, end) into pair_rec per global tile
+ *              (view tiles are numbered consecutively, view-major, row-major)
+ *   tile_order [n_tiles] uint32 work order of global tiles
+ * *n_tiles receives the total tile count of all views. */
+dbs_status dbs_bins_layout(void *bins, int64_t pair_capacity, const dbs_camera *cams /*[host]*/,
+                           int32_t n_views, const dbs_raster_cfg *cfg /*[host]*/,
+                           void **pair_rec, void **tile_range, void **tile_order,
+                           int64_t *n_tiles);
+
+const char *dbs_status_string(dbs_status s);
+
+/* Library version, e.g. "dbs 0.1 gfx950". */
+const char *dbs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DBS_H */

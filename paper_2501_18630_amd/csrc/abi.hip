@@ -1,0 +1,259 @@
+// C ABI of libdbs (include/dbs.h): argument validation, buffer layout and the
+// launch sequence of each call.  Nothing here allocates or synchronises.
+#include <math.h>
+#include <string.h>
+
+#include "dbs_internal.h"
+
+namespace dbs {
+
+int64_t total_tiles(const dbs_camera *cams, int32_t n_views, int tile_w, int tile_h)
+{
+    int64_t t = 0;
+    for (int32_t v = 0; v < n_views; ++v)
+        t += (int64_t)((cams[v].width + tile_w - 1) / tile_w) * ((cams[v].height + tile_h - 1) / tile_h);
+    return t;
+}
+
+static bool finite(float x) { return isfinite(x); }
+
+static dbs_status check_cams(const dbs_camera *cams, int32_t n_views)
+{
+    if (!cams || n_views < 1 || n_views > DBS_MAX_VIEWS) return DBS_ERR_INVALID_ARGUMENT;
+    for (int32_t v = 0; v < n_views; ++v) {
+        const dbs_camera &c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384) return DBS_ERR_INVALID_ARGUMENT;
+        if (!(c.near_plane > 0.0f) || !finite(c.near_plane)) return DBS_ERR_INVALID_ARGUMENT;
+        if (!finite(c.fx) || !finite(c.fy) || !finite(c.cx) || !finite(c.cy) || c.fx == 0.0f || c.fy == 0.0f)
+            return DBS_ERR_INVALID_ARGUMENT;
+        for (int k = 0; k < 12; ++k)
+            if (!finite(c.viewmat[k])) return DBS_ERR_INVALID_ARGUMENT;
+        for (int k = 0; k < 3; ++k)
+            if (!finite(c.background[k])) return DBS_ERR_INVALID_ARGUMENT;
+    }
+    return DBS_OK;
+}
+
+static dbs_status check_cfg(const dbs_raster_cfg *cfg)
+{
+    if (!cfg) return DBS_ERR_INVALID_ARGUMENT;
+    if (!(cfg->alpha_max > 0.0f && cfg->alpha_max < 1.0f)) return DBS_ERR_INVALID_ARGUMENT;
+    if (!(cfg->t_eps >= 0.0f && cfg->t_eps < 1.0f)) return DBS_ERR_INVALID_ARGUMENT;
+    if ((cfg->flags & ~DBS_FLAG_PERSISTENT) != 0) return DBS_ERR_INVALID_ARGUMENT;
+    if (!raster_supported(cfg->tile_w, cfg->tile_h, cfg->batch)) return DBS_ERR_UNSUPPORTED;
+    return DBS_OK;
+}
+
+static dbs_status check_sizes(int64_t n, int32_t n_views)
+{
+    if (n < 0) return DBS_ERR_INVALID_ARGUMENT;
+    if ((uint64_t)n * (uint64_t)n_views >= 0xffffffffull) return DBS_ERR_UNSUPPORTED;
+    return DBS_OK;
+}
+
+static dbs_status check_splats(const dbs_splats *s)
+{
+    if (!s) return DBS_ERR_INVALID_ARGUMENT;
+    if (s->n < 0) return DBS_ERR_INVALID_ARGUMENT;
+    if (s->m < 0 || s->m > DBS_MAX_LOBES) return DBS_ERR_UNSUPPORTED;
+    if (s->n > 0) {
+        if (!s->means || !s->scales || !s->quats || !s->opacities || !s->betas || !s->diffuse)
+            return DBS_ERR_INVALID_ARGUMENT;
+        if (s->m > 0 && (!s->lobe_angles || !s->lobe_colors || !s->lobe_betas)) return DBS_ERR_INVALID_ARGUMENT;
+    }
+    return DBS_OK;
+}
+
+static SplatPtrs splat_ptrs(const dbs_splats *s)
+{
+    SplatPtrs p;
+    p.means = s->means; p.scales = s->scales; p.quats = s->quats; p.opacities = s->opacities;
+    p.betas = s->betas; p.diffuse = s->diffuse; p.lobe_angles = s->lobe_angles;
+    p.lobe_colors = s->lobe_colors; p.lobe_betas = s->lobe_betas;
+    p.n = s->n; p.m = s->m;
+    return p;
+}
+
+static dbs_status hip_status(hipError_t e) { return e == hipSuccess ? DBS_OK : DBS_ERR_HIP; }
+
+#define DBS_TRY(x)                      \
+    do {                                \
+        dbs_status st_ = (x);           \
+        if (st_ != DBS_OK) return st_;  \
+    } while (0)
+
+}  // namespace dbs
+
+using namespace dbs;
+
+extern "C" {
+
+void dbs_default_cfg(dbs_raster_cfg *cfg)
+{
+    if (!cfg) return;
+    cfg->tile_w = 16;
+    cfg->tile_h = 16;
+    cfg->batch = 256;
+    cfg->t_eps = 1e-4f;
+    cfg->alpha_max = 0.99f;
+    cfg->flags = DBS_FLAG_PERSISTENT;
+}
+
+size_t dbs_projected_bytes(int64_t n, int32_t n_views)
+{
+    if (n < 0 || n_views < 1 || n_views > DBS_MAX_VIEWS) return 0;
+    return proj_layout(n, n_views).total;
+}
+
+size_t dbs_bins_bytes(int64_t pair_capacity, const dbs_camera *cams, int32_t n_views, const dbs_raster_cfg *cfg)
+{
+    if (pair_capacity < 0 || check_cams(cams, n_views) != DBS_OK || check_cfg(cfg) != DBS_OK) return 0;
+    return bins_layout(pair_capacity, total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h)).total;
+}
+
+size_t dbs_workspace_bytes(int64_t n, int32_t n_views, int64_t pair_capacity, const dbs_camera *cams,
+                           const dbs_raster_cfg *cfg)
+{
+    if (n < 0 || pair_capacity < 0 || check_cams(cams, n_views) != DBS_OK || check_cfg(cfg) != DBS_OK) return 0;
+    return work_layout(n, n_views, pair_capacity, total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h)).total;
+}
+
+dbs_status dbs_preprocess(const dbs_splats *splats, const dbs_camera *cams, int32_t n_views,
+                          const dbs_raster_cfg *cfg, void *projected, size_t projected_bytes, int64_t *counts,
+                          void *stream)
+{
+    DBS_TRY(check_splats(splats));
+    DBS_TRY(check_cams(cams, n_views));
+    DBS_TRY(check_cfg(cfg));
+    DBS_TRY(check_sizes(splats->n, n_views));
+    if (!projected) return DBS_ERR_INVALID_ARGUMENT;
+    if (projected_bytes < proj_layout(splats->n, n_views).total) return DBS_ERR_CAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+    ProjPtrs P = proj_ptrs(projected, splats->n, n_views);
+    DBS_TRY(hip_status(launch_upload_views(cams, n_views, cfg->tile_w, cfg->tile_h, P, splats->n, splats->m, s)));
+    return hip_status(launch_preprocess(splat_ptrs(splats), P, n_views, cfg->tile_w, cfg->tile_h, counts, s));
+}
+
+dbs_status dbs_bin_sort(const void *projected, const dbs_camera *cams, int32_t n_views, const dbs_raster_cfg *cfg,
+                        int64_t n, int64_t pair_capacity, void *bins, size_t bins_bytes, void *workspace,
+                        size_t workspace_bytes, int32_t *overflow, void *stream)
+{
+    DBS_TRY(check_cams(cams, n_views));
+    DBS_TRY(check_cfg(cfg));
+    DBS_TRY(check_sizes(n, n_views));
+    if (!projected || !bins || !workspace) return DBS_ERR_INVALID_ARGUMENT;
+    if (pair_capacity < 0) return DBS_ERR_INVALID_ARGUMENT;
+    if (pair_capacity > DBS_MAX_PAIRS) return DBS_ERR_UNSUPPORTED;
+    const int64_t n_tiles = total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h);
+    if (n_tiles >= 0xffffffffll) return DBS_ERR_UNSUPPORTED;
+    if (bins_bytes < bins_layout(pair_capacity, n_tiles).total) return DBS_ERR_CAPACITY;
+    if (workspace_bytes < work_layout(n, n_views, pair_capacity, n_tiles).total) return DBS_ERR_CAPACITY;
+    ProjPtrs P = proj_ptrs((void *)projected, n, n_views);
+    BinsPtrs B = bins_ptrs(bins, n_tiles);
+    return hip_status(launch_bin_sort(P, B, workspace, n, n_views, pair_capacity, n_tiles, cfg->tile_w,
+                                      cfg->tile_h, overflow, (hipStream_t)stream));
+}
+
+dbs_status dbs_render_fwd(const void *projected, const void *bins, const dbs_camera *cams, int32_t n_views,
+                          const dbs_raster_cfg *cfg, int64_t n, float *image, float *final_T, int32_t *last_index,
+                          void *stream)
+{
+    DBS_TRY(check_cams(cams, n_views));
+    DBS_TRY(check_cfg(cfg));
+    DBS_TRY(check_sizes(n, n_views));
+    if (!projected || !bins || !image || !final_T || !last_index) return DBS_ERR_INVALID_ARGUMENT;
+    const int64_t n_tiles = total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h);
+    ProjPtrs P = proj_ptrs((void *)projected, n, n_views);
+    BinsPtrs B = bins_ptrs((void *)bins, n_tiles);
+    return hip_status(launch_raster_fwd(P, B, n, n_views, n_tiles, *cfg, image, final_T, last_index,
+                                        (hipStream_t)stream));
+}
+
+dbs_status dbs_render_bwd(const dbs_splats *splats, const void *projected, const void *bins, const dbs_camera *cams,
+                          int32_t n_views, const dbs_raster_cfg *cfg, const float *final_T, const int32_t *last_index,
+                          const float *dL_dimage, dbs_splat_grads *grads, void *workspace, size_t workspace_bytes,
+                          void *stream)
+{
+    DBS_TRY(check_splats(splats));
+    DBS_TRY(check_cams(cams, n_views));
+    DBS_TRY(check_cfg(cfg));
+    DBS_TRY(check_sizes(splats->n, n_views));
+    if (!projected || !bins || !final_T || !last_index || !dL_dimage || !grads || !workspace)
+        return DBS_ERR_INVALID_ARGUMENT;
+    if (splats->n > 0) {
+        if (!grads->means || !grads->scales || !grads->quats || !grads->opacities || !grads->betas || !grads->diffuse)
+            return DBS_ERR_INVALID_ARGUMENT;
+        if (splats->m > 0 && (!grads->lobe_angles || !grads->lobe_colors || !grads->lobe_betas))
+            return DBS_ERR_INVALID_ARGUMENT;
+    }
+    const int64_t n = splats->n;
+    const int64_t n_tiles = total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h);
+    const WorkLayout L = work_layout(n, n_views, 0, n_tiles);
+    if (workspace_bytes < L.bwd_total) return DBS_ERR_CAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+    ProjPtrs P = proj_ptrs((void *)projected, n, n_views);
+    BinsPtrs B = bins_ptrs((void *)bins, n_tiles);
+    float *sgrad = (float *)((char *)workspace + L.sgrad);
+    DBS_TRY(hip_status(launch_zero_sgrad(P, n * n_views, sgrad, s)));
+    DBS_TRY(hip_status(launch_raster_bwd(P, B, n, n_views, n_tiles, *cfg, final_T, last_index, dL_dimage, sgrad, s)));
+    GradPtrs g;
+    g.means = grads->means; g.scales = grads->scales; g.quats = grads->quats; g.opacities = grads->opacities;
+    g.betas = grads->betas; g.diffuse = grads->diffuse; g.lobe_angles = grads->lobe_angles;
+    g.lobe_colors = grads->lobe_colors; g.lobe_betas = grads->lobe_betas;
+    return hip_status(launch_project_bwd(splat_ptrs(splats), P, n_views, sgrad, g, s));
+}
+
+dbs_status dbs_l1_loss(const float *image, const float *target, int64_t count, float scale, float *dL_dimage,
+                       float *loss, void *stream)
+{
+    if (count < 0) return DBS_ERR_INVALID_ARGUMENT;
+    if (count > 0 && (!image || !target || !dL_dimage)) return DBS_ERR_INVALID_ARGUMENT;
+    return hip_status(launch_l1_loss(image, target, count, scale, dL_dimage, loss, (hipStream_t)stream));
+}
+
+dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views, void **centre, void **conic,
+                                void **color, void **bbox, void **depth, void **ntiles, void **counts)
+{
+    if (!projected || n < 0 || n_views < 1 || n_views > DBS_MAX_VIEWS) return DBS_ERR_INVALID_ARGUMENT;
+    ProjPtrs P = proj_ptrs(projected, n, n_views);
+    if (centre) *centre = P.centre;
+    if (conic) *conic = P.conic;
+    if (color) *color = P.color;
+    if (bbox) *bbox = P.bbox;
+    if (depth) *depth = P.depth;
+    if (ntiles) *ntiles = P.ntiles;
+    if (counts) *counts = P.hdr->counts;
+    return DBS_OK;
+}
+
+dbs_status dbs_bins_layout(void *bins, int64_t pair_capacity, const dbs_camera *cams, int32_t n_views,
+                           const dbs_raster_cfg *cfg, void **pair_rec, void **tile_range, void **tile_order,
+                           int64_t *n_tiles)
+{
+    if (!bins || pair_capacity < 0) return DBS_ERR_INVALID_ARGUMENT;
+    DBS_TRY(check_cams(cams, n_views));
+    DBS_TRY(check_cfg(cfg));
+    const int64_t nt = total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h);
+    BinsPtrs B = bins_ptrs(bins, nt);
+    if (pair_rec) *pair_rec = B.pair_rec;
+    if (tile_range) *tile_range = B.tile_range;
+    if (tile_order) *tile_order = B.tile_order;
+    if (n_tiles) *n_tiles = nt;
+    return DBS_OK;
+}
+
+const char *dbs_status_string(dbs_status s)
+{
+    switch (s) {
+        case DBS_OK: return "ok";
+        case DBS_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case DBS_ERR_CAPACITY: return "buffer too small";
+        case DBS_ERR_HIP: return "HIP launch failure";
+        case DBS_ERR_UNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+const char *dbs_version(void) { return "dbs 0.1 gfx950"; }
+
+}  // extern "C"

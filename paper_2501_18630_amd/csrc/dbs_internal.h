@@ -1,0 +1,216 @@
+// Internal declarations shared by the HIP sources of libdbs (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dbs.h"
+
+namespace dbs {
+
+constexpr int kWave = 64;
+
+// One view as the kernels see it (written into `projected` by the preprocess).
+struct alignas(16) ViewDesc {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    float near_plane;
+    float bg[3];
+    int32_t width, height;
+    int32_t tiles_x, tiles_y;
+    int32_t tile_offset;   // first global tile id of the view
+    int32_t pad0;
+    int64_t pixel_offset;  // first flat pixel of the view
+    int64_t pad1[2];
+};
+static_assert(sizeof(ViewDesc) == 128, "ViewDesc layout");
+
+// Header at the start of `projected`.
+struct ProjHeader {
+    int64_t counts[2];     // visible records, pairs
+    int64_t n;
+    int32_t n_views, m;
+    int32_t tile_w, tile_h;
+    int32_t pad[22];
+};
+static_assert(sizeof(ProjHeader) == 128, "ProjHeader layout");
+
+// Header at the start of `bins`.
+struct BinsHeader {
+    int32_t overflow;
+    uint32_t n_vis;        // visible records
+    uint32_t n_pairs;      // pairs actually binned (0 on overflow)
+    uint32_t n_tiles;
+    uint32_t queue[4];     // persistent work queues: fwd head, fwd done, bwd head, bwd done
+    uint32_t pad[24];
+};
+static_assert(sizeof(BinsHeader) == 128, "BinsHeader layout");
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct ProjLayout {
+    size_t header, views, centre, conic, color, bbox, depth, ntiles, total;
+};
+inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
+    ProjLayout L;
+    size_t R = (size_t)n * (size_t)n_views, o = 0;
+    L.header = o; o = align_up(o + sizeof(ProjHeader));
+    L.views = o;  o = align_up(o + sizeof(ViewDesc) * (size_t)n_views);
+    L.centre = o; o = align_up(o + 16 * R);
+    L.conic = o;  o = align_up(o + 16 * R);
+    L.color = o;  o = align_up(o + 16 * R);
+    L.bbox = o;   o = align_up(o + 8 * R);
+    L.depth = o;  o = align_up(o + 4 * R);
+    L.ntiles = o; o = align_up(o + 4 * R);
+    L.total = o;
+    return L;
+}
+
+// Capacity-independent parts first, so that the tile ranges and work order
+// can be located from the tile count alone.
+struct BinsLayout {
+    size_t header, tile_range, tile_order, pair_rec, total;
+};
+inline BinsLayout bins_layout(int64_t cap, int64_t n_tiles) {
+    BinsLayout L;
+    size_t o = 0;
+    L.header = o;     o = align_up(o + sizeof(BinsHeader));
+    L.tile_range = o; o = align_up(o + 8 * (size_t)n_tiles);
+    L.tile_order = o; o = align_up(o + 4 * (size_t)n_tiles);
+    L.pair_rec = o;   o = align_up(o + 4 * (size_t)cap);
+    L.total = o;
+    return L;
+}
+
+// Radix sort / scan geometry.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // elements per block
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kScanTile = 4096;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct WorkLayout {
+    // bin/sort phase
+    size_t keys_a, vals_a, keys_b, vals_b, pair_off, pkeys_a, pkeys_b, pvals_b, hist, partials,
+        tkeys_a, tvals_a, tkeys_b, sort_total;
+    // backward phase
+    size_t sgrad, bwd_total;
+    size_t total;
+    int64_t hist_blocks;  // max sort blocks of any sort
+};
+inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n_tiles) {
+    WorkLayout L;
+    size_t R = (size_t)n * (size_t)n_views, o = 0;
+    int64_t maxn = (int64_t)R;
+    if (cap > maxn) maxn = cap;
+    if (n_tiles > maxn) maxn = n_tiles;
+    L.hist_blocks = ceil_div(maxn > 0 ? maxn : 1, kSortTile);
+    size_t hist_n = (size_t)L.hist_blocks * kRadix;
+    size_t part_n = (size_t)ceil_div((int64_t)(hist_n > R + 1 ? hist_n : R + 1), kScanTile) + 64;
+    L.keys_a = o;   o = align_up(o + 4 * R);
+    L.vals_a = o;   o = align_up(o + 4 * R);
+    L.keys_b = o;   o = align_up(o + 4 * R);
+    L.vals_b = o;   o = align_up(o + 4 * R);
+    L.pair_off = o; o = align_up(o + 4 * (R + 1));
+    L.pkeys_a = o;  o = align_up(o + 4 * (size_t)cap);
+    L.pkeys_b = o;  o = align_up(o + 4 * (size_t)cap);
+    L.pvals_b = o;  o = align_up(o + 4 * (size_t)cap);
+    L.hist = o;     o = align_up(o + 4 * hist_n);
+    L.partials = o; o = align_up(o + 4 * part_n);
+    L.tkeys_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
+    L.tvals_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
+    L.tkeys_b = o;  o = align_up(o + 4 * (size_t)n_tiles);
+    L.sort_total = o;
+    size_t b = 0;
+    L.sgrad = b;    b = align_up(b + 48 * R);
+    L.bwd_total = b;
+    L.total = L.sort_total > L.bwd_total ? L.sort_total : L.bwd_total;
+    return L;
+}
+
+// Device pointers of the splat parameters.
+struct SplatPtrs {
+    const float *means, *scales, *quats, *opacities, *betas, *diffuse;
+    const float *lobe_angles, *lobe_colors, *lobe_betas;
+    int64_t n;
+    int32_t m;
+};
+struct GradPtrs {
+    float *means, *scales, *quats, *opacities, *betas, *diffuse;
+    float *lobe_angles, *lobe_colors, *lobe_betas;
+};
+
+// Pointers into `projected`.
+struct ProjPtrs {
+    ProjHeader *hdr;
+    ViewDesc *views;
+    float4 *centre, *conic, *color;
+    short4 *bbox;
+    uint32_t *depth, *ntiles;
+};
+inline ProjPtrs proj_ptrs(void *base, int64_t n, int32_t n_views) {
+    ProjLayout L = proj_layout(n, n_views);
+    char *b = (char *)base;
+    ProjPtrs p;
+    p.hdr = (ProjHeader *)(b + L.header);
+    p.views = (ViewDesc *)(b + L.views);
+    p.centre = (float4 *)(b + L.centre);
+    p.conic = (float4 *)(b + L.conic);
+    p.color = (float4 *)(b + L.color);
+    p.bbox = (short4 *)(b + L.bbox);
+    p.depth = (uint32_t *)(b + L.depth);
+    p.ntiles = (uint32_t *)(b + L.ntiles);
+    return p;
+}
+
+struct BinsPtrs {
+    BinsHeader *hdr;
+    uint32_t *pair_rec;
+    uint2 *tile_range;
+    uint32_t *tile_order;
+};
+inline BinsPtrs bins_ptrs(void *base, int64_t n_tiles) {
+    BinsLayout L = bins_layout(0, n_tiles);
+    char *b = (char *)base;
+    BinsPtrs p;
+    p.hdr = (BinsHeader *)(b + L.header);
+    p.pair_rec = (uint32_t *)(b + L.pair_rec);
+    p.tile_range = (uint2 *)(b + L.tile_range);
+    p.tile_order = (uint32_t *)(b + L.tile_order);
+    return p;
+}
+
+// Host-side helpers (abi.hip).
+int64_t total_tiles(const dbs_camera *cams, int32_t n_views, int tile_w, int tile_h);
+
+// ---- launchers (one per source file) ----
+// preprocess.hip
+hipError_t launch_upload_views(const dbs_camera *cams, int32_t n_views, int tile_w, int tile_h,
+                               ProjPtrs P, int64_t n, int32_t m, hipStream_t s);
+hipError_t launch_preprocess(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, int tile_w,
+                             int tile_h, int64_t *counts_out, hipStream_t s);
+// sort.hip
+hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_t n_views,
+                           int64_t cap, int64_t n_tiles, int tile_w, int tile_h,
+                           int32_t *overflow_out, hipStream_t s);
+// raster.hip
+bool raster_supported(int tw, int th, int batch);
+hipError_t launch_raster_fwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views, int64_t n_tiles,
+                             const dbs_raster_cfg &cfg, float *image, float *final_T,
+                             int32_t *last_index, hipStream_t s);
+hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views, int64_t n_tiles,
+                             const dbs_raster_cfg &cfg, const float *final_T,
+                             const int32_t *last_index, const float *dL_dimage, float *sgrad,
+                             hipStream_t s);
+// project_bwd.hip (also the L1 loss)
+hipError_t launch_zero_sgrad(ProjPtrs P, int64_t R, float *sgrad, hipStream_t s);
+hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, const float *sgrad,
+                              const GradPtrs &g, hipStream_t s);
+hipError_t launch_l1_loss(const float *image, const float *target, int64_t count, float scale,
+                          float *grad, float *loss, hipStream_t s);
+
+}  // namespace dbs

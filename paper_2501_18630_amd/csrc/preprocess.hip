@@ -1,0 +1,243 @@
+// Per-(view, splat) projection and Spherical Beta colour.
+//
+// Sec. 3.2: Sigma = R S S^T R^T from the quaternion and scale, projected
+// covariance Sigma' = J W Sigma W^T J^T (J the Jacobian of the pinhole map at
+// the splat centre), centre mu', and the conic Sigma'^{-1} that Eq. (5)
+// evaluates.  The Beta kernel is exactly zero outside r^2 < 1 (Sec. 3.1,
+// Eq. 2), so the support's bounding box is mu' +- (sqrt(Sigma'_00),
+// sqrt(Sigma'_11)); the record lists the pixel centres inside it and the
+// number of tiles it overlaps.  Sec. 3.3, Eq. (8): colour = c0 + sum_m
+// B(1 - R_m . V; b_m) c_m with B(x; b) = (1 - x)^(4 e^b).
+//
+// One thread per splat loops over the views, so every parameter is read from
+// HBM once per call however many views are rendered.  Geometry is computed in
+// FP64 (exact products of the FP32 inputs, then rounded once): the pixel box
+// and the depth key are integer decisions that must not depend on FP32
+// rounding, and the centre is kept as an FP32 hi/lo pair so that pixel
+// offsets can be formed without the absolute-coordinate rounding of a single
+// FP32 value (ulp(1400) ~ 1.2e-4 px).
+#include "dbs_internal.h"
+
+namespace dbs {
+
+namespace {
+
+constexpr int kUploadViews = 8;
+struct ViewUpload {
+    ViewDesc v[kUploadViews];
+    int32_t first, count;
+};
+
+__global__ void upload_views_kernel(ViewUpload up, ViewDesc *views, ProjHeader *hdr, int64_t n,
+                                    int32_t n_views, int32_t m, int32_t tw, int32_t th, int32_t reset)
+{
+    int t = threadIdx.x;
+    if (t < up.count) views[up.first + t] = up.v[t];
+    if (reset && t == 0) {
+        hdr->counts[0] = 0;
+        hdr->counts[1] = 0;
+        hdr->n = n;
+        hdr->n_views = n_views;
+        hdr->m = m;
+        hdr->tile_w = tw;
+        hdr->tile_h = th;
+    }
+}
+
+__device__ inline uint64_t wave_sum_u64(uint64_t v)
+{
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
+                                                         int32_t tw, int32_t th)
+{
+    const int64_t n = sp.n;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t vis = 0, pairs = 0;
+    if (i < n) {
+        const double mu[3] = {sp.means[3 * i], sp.means[3 * i + 1], sp.means[3 * i + 2]};
+        // rotation of the normalised quaternion (w, x, y, z)
+        double q0 = sp.quats[4 * i], q1 = sp.quats[4 * i + 1], q2 = sp.quats[4 * i + 2],
+               q3 = sp.quats[4 * i + 3];
+        double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        bool ok = qn > 0.0;
+        double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+        double Rq[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                        2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                        2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+        double s2[3];
+        for (int k = 0; k < 3; ++k) {
+            double s = sp.scales[3 * i + k];
+            s2[k] = s * s;
+        }
+        // Sigma = R diag(s^2) R^T (symmetric, 6 entries)
+        double Sig[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b) {
+                double acc = Rq[3 * a] * s2[0] * Rq[3 * b] + Rq[3 * a + 1] * s2[1] * Rq[3 * b + 1] +
+                             Rq[3 * a + 2] * s2[2] * Rq[3 * b + 2];
+                Sig[a][b] = acc;
+                Sig[b][a] = acc;
+            }
+        const float opac = sp.opacities[i];
+        const float beta = 4.0f * expf(sp.betas[i]);
+        const float c0r = sp.diffuse[3 * i], c0g = sp.diffuse[3 * i + 1], c0b = sp.diffuse[3 * i + 2];
+        float lr[M > 0 ? M : 1][3], lc[M > 0 ? M : 1][3], lbeta[M > 0 ? M : 1];
+#pragma unroll
+        for (int mm = 0; mm < M; ++mm) {
+            const int64_t l = i * M + mm;
+            float st, ct, sph, cph;
+            sincosf(sp.lobe_angles[2 * l], &st, &ct);
+            sincosf(sp.lobe_angles[2 * l + 1], &sph, &cph);
+            lr[mm][0] = st * cph;
+            lr[mm][1] = st * sph;
+            lr[mm][2] = ct;
+            for (int c = 0; c < 3; ++c) lc[mm][c] = sp.lobe_colors[3 * l + c];
+            lbeta[mm] = 4.0f * expf(sp.lobe_betas[l]);
+        }
+
+        for (int32_t v = 0; v < n_views; ++v) {
+            const ViewDesc &V = P.views[v];
+            const int64_t rec = (int64_t)v * n + i;
+            const double W[9] = {V.R[0], V.R[1], V.R[2], V.R[3], V.R[4], V.R[5], V.R[6], V.R[7], V.R[8]};
+            double tc[3];
+            for (int r = 0; r < 3; ++r)
+                tc[r] = W[3 * r] * mu[0] + W[3 * r + 1] * mu[1] + W[3 * r + 2] * mu[2] + (double)V.t[r];
+            const float depth_f = (float)tc[2];
+            P.depth[rec] = __float_as_uint(depth_f);
+            uint32_t ntiles = 0;
+            short4 bb = make_short4(0, -1, 0, -1);
+            if (ok && tc[2] > (double)V.near_plane) {
+                const double tx = tc[0], ty = tc[1], tz = tc[2];
+                const double fx = V.fx, fy = V.fy;
+                const double J00 = fx / tz, J02 = -fx * tx / (tz * tz);
+                const double J11 = fy / tz, J12 = -fy * ty / (tz * tz);
+                // M = J W (2x3)
+                double Mm[2][3];
+                for (int b = 0; b < 3; ++b) {
+                    Mm[0][b] = J00 * W[b] + J02 * W[6 + b];
+                    Mm[1][b] = J11 * W[3 + b] + J12 * W[6 + b];
+                }
+                // T = M Sigma (2x3), Sigma' = T M^T
+                double Tm[2][3];
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        Tm[a][b] = Mm[a][0] * Sig[0][b] + Mm[a][1] * Sig[1][b] + Mm[a][2] * Sig[2][b];
+                const double c00 = Tm[0][0] * Mm[0][0] + Tm[0][1] * Mm[0][1] + Tm[0][2] * Mm[0][2];
+                const double c01 = Tm[0][0] * Mm[1][0] + Tm[0][1] * Mm[1][1] + Tm[0][2] * Mm[1][2];
+                const double c11 = Tm[1][0] * Mm[1][0] + Tm[1][1] * Mm[1][1] + Tm[1][2] * Mm[1][2];
+                const double det = c00 * c11 - c01 * c01;
+                if (det > 0.0) {
+                    const double mx = fx * tx / tz + (double)V.cx;
+                    const double my = fy * ty / tz + (double)V.cy;
+                    const double ex = sqrt(c00), ey = sqrt(c11);
+                    double xl = ceil(mx - ex - 0.5), xh = floor(mx + ex - 0.5);
+                    double yl = ceil(my - ey - 0.5), yh = floor(my + ey - 0.5);
+                    xl = fmax(xl, 0.0);
+                    yl = fmax(yl, 0.0);
+                    xh = fmin(xh, (double)(V.width - 1));
+                    yh = fmin(yh, (double)(V.height - 1));
+                    if (xl <= xh && yl <= yh) {
+                        const int ixl = (int)xl, ixh = (int)xh, iyl = (int)yl, iyh = (int)yh;
+                        bb = make_short4((short)ixl, (short)ixh, (short)iyl, (short)iyh);
+                        ntiles = (uint32_t)((ixh / tw - ixl / tw + 1) * (iyh / th - iyl / th + 1));
+                        const float hx = (float)mx, hy = (float)my;
+                        P.centre[rec] = make_float4(hx, hy, (float)(mx - (double)hx), (float)(my - (double)hy));
+                        P.conic[rec] = make_float4((float)(c11 / det), (float)(-c01 / det), (float)(c00 / det), opac);
+                        // Spherical Beta colour; V = (mu - camera centre) / |.|
+                        double cp[3];
+                        for (int k = 0; k < 3; ++k)
+                            cp[k] = -(W[k] * (double)V.t[0] + W[3 + k] * (double)V.t[1] + W[6 + k] * (double)V.t[2]);
+                        double vx = mu[0] - cp[0], vy = mu[1] - cp[1], vz = mu[2] - cp[2];
+                        double vl = sqrt(vx * vx + vy * vy + vz * vz);
+                        const float dx = (float)(vx / vl), dy = (float)(vy / vl), dz = (float)(vz / vl);
+                        float cr = c0r, cg = c0g, cb = c0b;
+#pragma unroll
+                        for (int mm = 0; mm < M; ++mm) {
+                            const float d = lr[mm][0] * dx + lr[mm][1] * dy + lr[mm][2] * dz;
+                            if (d > 0.0f) {
+                                const float wgt = exp2f(lbeta[mm] * log2f(d));
+                                cr += wgt * lc[mm][0];
+                                cg += wgt * lc[mm][1];
+                                cb += wgt * lc[mm][2];
+                            }
+                        }
+                        P.color[rec] = make_float4(cr, cg, cb, beta);
+                        vis += 1;
+                        pairs += ntiles;
+                    }
+                }
+            }
+            P.bbox[rec] = bb;
+            P.ntiles[rec] = ntiles;
+        }
+    }
+    vis = wave_sum_u64(vis);
+    pairs = wave_sum_u64(pairs);
+    if ((threadIdx.x & (kWave - 1)) == 0 && (vis | pairs)) {
+        atomicAdd((unsigned long long *)&P.hdr->counts[0], (unsigned long long)vis);
+        atomicAdd((unsigned long long *)&P.hdr->counts[1], (unsigned long long)pairs);
+    }
+}
+
+__global__ void copy_counts_kernel(const ProjHeader *hdr, int64_t *out)
+{
+    if (threadIdx.x < 2) out[threadIdx.x] = hdr->counts[threadIdx.x];
+}
+
+}  // namespace
+
+hipError_t launch_upload_views(const dbs_camera *cams, int32_t n_views, int tile_w, int tile_h,
+                               ProjPtrs P, int64_t n, int32_t m, hipStream_t s)
+{
+    int32_t tile_off = 0;
+    int64_t pix_off = 0;
+    for (int32_t first = 0; first < n_views; first += kUploadViews) {
+        ViewUpload up{};
+        up.first = first;
+        up.count = n_views - first < kUploadViews ? n_views - first : kUploadViews;
+        for (int k = 0; k < up.count; ++k) {
+            const dbs_camera &c = cams[first + k];
+            ViewDesc &d = up.v[k];
+            for (int r = 0; r < 3; ++r) {
+                for (int col = 0; col < 3; ++col) d.R[3 * r + col] = c.viewmat[4 * r + col];
+                d.t[r] = c.viewmat[4 * r + 3];
+                d.bg[r] = c.background[r];
+            }
+            d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+            d.near_plane = c.near_plane;
+            d.width = c.width; d.height = c.height;
+            d.tiles_x = (c.width + tile_w - 1) / tile_w;
+            d.tiles_y = (c.height + tile_h - 1) / tile_h;
+            d.tile_offset = tile_off;
+            d.pixel_offset = pix_off;
+            tile_off += d.tiles_x * d.tiles_y;
+            pix_off += (int64_t)c.width * c.height;
+        }
+        upload_views_kernel<<<1, 64, 0, s>>>(up, P.views, P.hdr, n, n_views, m, tile_w, tile_h,
+                                             first == 0 ? 1 : 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, int tile_w,
+                             int tile_h, int64_t *counts_out, hipStream_t s)
+{
+    if (sp.n > 0) {
+        dim3 grid((unsigned)ceil_div(sp.n, 256));
+        switch (sp.m) {
+#define DBS_PRE(MM) case MM: preprocess_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, tile_w, tile_h); break;
+            DBS_PRE(0) DBS_PRE(1) DBS_PRE(2) DBS_PRE(3) DBS_PRE(4)
+            DBS_PRE(5) DBS_PRE(6) DBS_PRE(7) DBS_PRE(8)
+#undef DBS_PRE
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (counts_out) copy_counts_kernel<<<1, 64, 0, s>>>(P.hdr, counts_out);
+    return hipGetLastError();
+}
+
+}  // namespace dbs

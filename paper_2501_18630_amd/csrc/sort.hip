@@ -1,0 +1,471 @@
+// Tile binning and (view, tile, depth, id) ordering.
+//
+// Sec. 3.2 composites the primitives overlapping a pixel "after sorting by
+// depth".  Instead of one wide radix sort of (tile | depth) keys over all
+// pairs, the order is built in two narrow stable sorts:
+//   1. compact the visible (view, splat) records and radix-sort them by the
+//      fp32 bits of their depth (32 bits, over P records); stability keeps
+//      equal depths in record order, i.e. by splat index within a view;
+//   2. emit one (global tile id, record) pair per overlapped tile, walking
+//      the records in depth order, and radix-sort the pairs by tile id only
+//      (ceil(log2 tiles) bits, over K pairs); stability keeps the depth
+//      order inside each tile.
+// The result is exactly the lexicographic (view, tile, depth bits, splat id)
+// order, at 2-3 narrow passes over the K pairs instead of 6-7 wide ones.
+//
+// The radix sort is a classic LSD sort with 8-bit digits: per-block digit
+// histograms (upsweep), a device-wide exclusive scan of the digit-major
+// histogram, and a stable scatter (downsweep) that ranks each block's keys in
+// LDS with wave ballots and writes them out digit-contiguous.  Element counts
+// are read from device memory, so the whole pipeline runs without a host
+// round trip and can be captured in a graph.
+#include "dbs_internal.h"
+
+namespace dbs {
+
+namespace {
+
+struct Count {
+    const uint32_t *dev;  // if non-null, n = min(*dev, host)
+    int64_t host;
+    __device__ inline int64_t get() const
+    {
+        if (dev) {
+            int64_t d = *dev;
+            return d < host ? d : host;
+        }
+        return host;
+    }
+};
+
+__device__ inline uint64_t lanemask_lt()
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Exclusive scan of one value per thread across a block of kSortThreads.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp /*[kSortThreads/kWave + 1]*/,
+                                                uint32_t *total)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) s_tmp[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k < kSortThreads / kWave; ++k) {
+            uint32_t c = s_tmp[k];
+            s_tmp[k] = acc;
+            acc += c;
+        }
+        s_tmp[kSortThreads / kWave] = acc;
+    }
+    __syncthreads();
+    uint32_t r = s_tmp[w] + x - v;
+    if (total) *total = s_tmp[kSortThreads / kWave];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------- device-wide scan
+// Exclusive scan of Load(i), i < n, in tiles of kScanTile = 256 threads x 16
+// items (blocked per thread); Store(i, prefix, value) receives the result.
+
+template <class Load>
+__global__ __launch_bounds__(kSortThreads) void scan_reduce_kernel(Load ld, Count cnt, uint32_t *partials)
+{
+    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
+    const int64_t n = cnt.get();
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 16;
+    uint32_t acc = 0;
+#pragma unroll 4
+    for (int k = 0; k < 16; ++k)
+        if (base + k < n) acc += ld(base + k);
+    uint32_t total;
+    block_exclusive_scan(acc, s_tmp, &total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// Single-block exclusive scan of partials[0..nb), in place.
+__global__ __launch_bounds__(1024) void scan_partials_kernel(uint32_t *partials, int64_t nb)
+{
+    __shared__ uint32_t s_w[1024 / kWave + 1];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        uint32_t v = i < nb ? partials[i] : 0, x = v;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            uint32_t y = __shfl_up(x, off, kWave);
+            if (lane >= off) x += y;
+        }
+        if (lane == kWave - 1) s_w[w] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0;
+            for (int k = 0; k < 1024 / kWave; ++k) {
+                uint32_t c = s_w[k];
+                s_w[k] = acc;
+                acc += c;
+            }
+            s_w[1024 / kWave] = acc;
+        }
+        __syncthreads();
+        if (i < nb) partials[i] = s_carry + s_w[w] + x - v;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += s_w[1024 / kWave];
+        __syncthreads();
+    }
+}
+
+template <class Load, class Store>
+__global__ __launch_bounds__(kSortThreads) void scan_apply_kernel(Load ld, Store st, Count cnt,
+                                                                  const uint32_t *partials)
+{
+    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
+    const int64_t n = cnt.get();
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 16;
+    uint32_t v[16], acc = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        v[k] = base + k < n ? ld(base + k) : 0u;
+        acc += v[k];
+    }
+    uint32_t pre = block_exclusive_scan(acc, s_tmp, nullptr) + partials[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (base + k < n) st(base + k, pre, v[k]);
+        pre += v[k];
+    }
+}
+
+template <class Load, class Store>
+hipError_t device_scan(Load ld, Store st, Count cnt, uint32_t *partials, hipStream_t s)
+{
+    const int64_t nb = ceil_div(cnt.host > 0 ? cnt.host : 1, kScanTile);
+    scan_reduce_kernel<Load><<<(unsigned)nb, kSortThreads, 0, s>>>(ld, cnt, partials);
+    scan_partials_kernel<<<1, 1024, 0, s>>>(partials, nb);
+    scan_apply_kernel<Load, Store><<<(unsigned)nb, kSortThreads, 0, s>>>(ld, st, cnt, partials);
+    return hipGetLastError();
+}
+
+struct LoadArray {
+    const uint32_t *a;
+    __device__ uint32_t operator()(int64_t i) const { return a[i]; }
+};
+struct StoreArray {
+    uint32_t *a;
+    __device__ void operator()(int64_t i, uint32_t pre, uint32_t) const { a[i] = pre; }
+};
+
+// ---------------------------------------------------------------- radix sort
+
+// 8-bit digit match across the wave: mask of valid lanes holding digit d.
+__device__ inline uint64_t match_digit(uint32_t d, bool valid)
+{
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+__global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint32_t *keys, Count cnt,
+                                                                     int shift, uint32_t *hist, int64_t nblocks)
+{
+    __shared__ uint32_t s_cnt[kRadix];
+    const int64_t n = cnt.get();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    if (base < n) {
+        for (int k = 0; k < kSortItems; ++k) {
+            const int64_t e = base + (int64_t)k * kSortThreads + threadIdx.x;
+            const bool valid = e < n;
+            const uint32_t d = valid ? (keys[e] >> shift) & (kRadix - 1) : 0u;
+            const uint64_t peers = match_digit(d, valid);
+            if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
+        }
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
+    const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
+    uint32_t *__restrict__ vals_out, Count cnt, int shift, const uint32_t *hist, int64_t nblocks)
+{
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint32_t s_wcnt[2][kSortThreads / kWave][kRadix];
+    __shared__ uint32_t s_run[kRadix];
+    __shared__ uint32_t s_start[kRadix];
+    __shared__ uint32_t s_goff[kRadix];
+    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
+
+    const int64_t n = cnt.get();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    if (base >= n) return;  // uniform across the block
+    const int t = threadIdx.x, w = t / kWave;
+    s_run[t] = 0;
+    s_goff[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int ww = 0; ww < kSortThreads / kWave; ++ww) s_wcnt[b][ww][t] = 0;
+    __syncthreads();
+
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t e = base + (int64_t)k * kSortThreads + t;
+        const bool valid = e < n;
+        key[k] = valid ? keys_in[e] : 0u;
+        val[k] = valid ? vals_in[e] : 0u;
+        const uint32_t d = (key[k] >> shift) & (kRadix - 1);
+        const uint64_t peers = match_digit(d, valid);
+        const uint32_t in_wave = (uint32_t)__popcll(peers & lt);
+        const int buf = k & 1;
+        if (valid && in_wave == 0) s_wcnt[buf][w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {   // thread t owns digit t: prefix over the waves of this round
+            uint32_t r = s_run[t];
+#pragma unroll
+            for (int ww = 0; ww < kSortThreads / kWave; ++ww) {
+                const uint32_t c = s_wcnt[buf][ww][t];
+                s_wcnt[buf][ww][t] = r;
+                r += c;
+            }
+            s_run[t] = r;
+#pragma unroll
+            for (int ww = 0; ww < kSortThreads / kWave; ++ww) s_wcnt[buf ^ 1][ww][t] = 0;
+        }
+        __syncthreads();
+        rank[k] = s_wcnt[buf][w][d] + in_wave;
+    }
+    uint32_t start = block_exclusive_scan(s_run[t], s_tmp, nullptr);
+    s_start[t] = start;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t e = base + (int64_t)k * kSortThreads + t;
+        if (e < n) {
+            const uint32_t d = (key[k] >> shift) & (kRadix - 1);
+            const uint32_t pos = s_start[d] + rank[k];
+            s_keys[pos] = key[k];
+            s_vals[pos] = val[k];
+        }
+    }
+    __syncthreads();
+    const int64_t cnt_blk = n - base < kSortTile ? n - base : kSortTile;
+    for (int j = t; j < cnt_blk; j += kSortThreads) {
+        const uint32_t kk = s_keys[j];
+        const uint32_t d = (kk >> shift) & (kRadix - 1);
+        const uint32_t o = s_goff[d] + (uint32_t)j - s_start[d];
+        keys_out[o] = kk;
+        vals_out[o] = s_vals[j];
+    }
+}
+
+// Stable sort of (keys, vals) by key bits [bit_lo, bit_hi); ping-pongs
+// between the a and b buffers and reports where the result ended up.
+hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Count cnt, int bit_lo,
+                      int bit_hi, uint32_t *hist, uint32_t *partials, hipStream_t s, bool *result_in_b)
+{
+    const int64_t nblocks = ceil_div(cnt.host > 0 ? cnt.host : 1, kSortTile);
+    bool in_b = false;
+    for (int shift = bit_lo; shift < bit_hi; shift += kRadixBits) {
+        const uint32_t *kin = in_b ? kb : ka, *vin = in_b ? vb : va;
+        uint32_t *kout = in_b ? ka : kb, *vout = in_b ? va : vb;
+        radix_upsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, hist, nblocks);
+        hipError_t e = device_scan(LoadArray{hist}, StoreArray{hist}, Count{nullptr, nblocks * kRadix},
+                                   partials, s);
+        if (e != hipSuccess) return e;
+        radix_downsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, cnt, shift,
+                                                                          hist, nblocks);
+        in_b = !in_b;
+    }
+    *result_in_b = in_b;
+    return hipGetLastError();
+}
+
+int radix_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
+
+// ---------------------------------------------------------------- binning kernels
+
+__global__ void finalize_counts_kernel(const ProjHeader *ph, BinsHeader *bh, int64_t cap, uint32_t n_tiles,
+                                       int32_t *overflow_out)
+{
+    if (threadIdx.x != 0) return;
+    const int64_t vis = ph->counts[0], pairs = ph->counts[1];
+    const int32_t ovf = pairs > cap ? 1 : 0;
+    bh->overflow = ovf;
+    bh->n_vis = (uint32_t)vis;
+    bh->n_pairs = ovf ? 0u : (uint32_t)pairs;
+    bh->n_tiles = n_tiles;
+    for (int k = 0; k < 4; ++k) bh->queue[k] = 0;
+    if (overflow_out) *overflow_out = ovf;
+}
+
+struct LoadVisible {
+    const uint32_t *ntiles;
+    __device__ uint32_t operator()(int64_t i) const { return ntiles[i] > 0 ? 1u : 0u; }
+};
+struct StoreCompact {
+    const uint32_t *depth;
+    uint32_t *keys, *vals;
+    __device__ void operator()(int64_t i, uint32_t pre, uint32_t v) const
+    {
+        if (v) {
+            keys[pre] = depth[i];
+            vals[pre] = (uint32_t)i;
+        }
+    }
+};
+struct LoadTilesOfSorted {
+    const uint32_t *ntiles, *sorted_rec;
+    __device__ uint32_t operator()(int64_t j) const { return ntiles[sorted_rec[j]]; }
+};
+
+__global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, const uint32_t *sorted_rec,
+                                                         const uint32_t *pair_off, const short4 *bbox,
+                                                         const ViewDesc *views, uint32_t n, int tw, int th,
+                                                         uint32_t *pkeys, uint32_t *pvals)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (bh->overflow || j >= (int64_t)bh->n_vis) return;
+    const uint32_t rec = sorted_rec[j];
+    const uint32_t v = rec / n;
+    const short4 b = bbox[rec];
+    const ViewDesc &V = views[v];
+    const int tx0 = b.x / tw, tx1 = b.y / tw, ty0 = b.z / th, ty1 = b.w / th;
+    uint32_t o = pair_off[j];
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        const uint32_t row = (uint32_t)V.tile_offset + (uint32_t)(ty * V.tiles_x);
+        for (int tx = tx0; tx <= tx1; ++tx, ++o) {
+            pkeys[o] = row + (uint32_t)tx;
+            pvals[o] = rec;
+        }
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t count, uint32_t value)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+__global__ __launch_bounds__(256) void tile_ranges_kernel(const BinsHeader *bh, const uint32_t *skeys,
+                                                          uint2 *ranges)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t K = bh->n_pairs;
+    if (j >= K) return;
+    const uint32_t k = skeys[j];
+    if (j == 0 || skeys[j - 1] != k) ranges[k].x = (uint32_t)j;
+    if (j == K - 1 || skeys[j + 1] != k) ranges[k].y = (uint32_t)(j + 1);
+}
+
+// Heaviest tiles first: key = 0xffff - min(pairs, 0xffff).
+__global__ void tile_cost_keys_kernel(const uint2 *ranges, int64_t n_tiles, uint32_t *keys, uint32_t *vals)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint2 r = ranges[t];
+    const uint32_t c = r.y - r.x;
+    keys[t] = 0xffffu - (c < 0xffffu ? c : 0xffffu);
+    vals[t] = (uint32_t)t;
+}
+
+int bits_for(int64_t count)
+{
+    int b = 0;
+    while (b < 32 && ((int64_t)1 << b) < count) ++b;
+    return b;
+}
+
+}  // namespace
+
+hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_t n_views, int64_t cap,
+                           int64_t n_tiles, int tile_w, int tile_h, int32_t *overflow_out, hipStream_t s)
+{
+    const WorkLayout L = work_layout(n, n_views, cap, n_tiles);
+    char *wb = (char *)work;
+    uint32_t *keys_a = (uint32_t *)(wb + L.keys_a), *vals_a = (uint32_t *)(wb + L.vals_a);
+    uint32_t *keys_b = (uint32_t *)(wb + L.keys_b), *vals_b = (uint32_t *)(wb + L.vals_b);
+    uint32_t *pair_off = (uint32_t *)(wb + L.pair_off);
+    uint32_t *pkeys_a = (uint32_t *)(wb + L.pkeys_a), *pkeys_b = (uint32_t *)(wb + L.pkeys_b);
+    uint32_t *pvals_b = (uint32_t *)(wb + L.pvals_b);
+    uint32_t *hist = (uint32_t *)(wb + L.hist), *partials = (uint32_t *)(wb + L.partials);
+    uint32_t *tkeys_a = (uint32_t *)(wb + L.tkeys_a), *tvals_tmp = (uint32_t *)(wb + L.tvals_a);
+    uint32_t *tkeys_b = (uint32_t *)(wb + L.tkeys_b);
+    const int64_t R = n * n_views;
+    hipError_t e;
+
+    finalize_counts_kernel<<<1, 64, 0, s>>>(P.hdr, B.hdr, cap, (uint32_t)n_tiles, overflow_out);
+
+    // 1. compact visible records, then sort them by depth bits
+    if (R > 0) {
+        e = device_scan(LoadVisible{P.ntiles}, StoreCompact{P.depth, keys_a, vals_a}, Count{nullptr, R},
+                        partials, s);
+        if (e != hipSuccess) return e;
+    }
+    const Count vis_cnt{&B.hdr->n_vis, R};
+    bool depth_in_b = false;
+    if (R > 0) {
+        e = radix_sort(keys_a, vals_a, keys_b, vals_b, vis_cnt, 0, 32, hist, partials, s, &depth_in_b);
+        if (e != hipSuccess) return e;
+    }
+    const uint32_t *sorted_rec = depth_in_b ? vals_b : vals_a;
+
+    // 2. pair offsets in depth order, emit (tile, record) pairs
+    const int tile_bits = bits_for(n_tiles);
+    const bool odd = radix_passes(tile_bits) % 2 == 1;
+    uint32_t *emit_vals = odd ? pvals_b : B.pair_rec;
+    uint32_t *other_vals = odd ? B.pair_rec : pvals_b;
+    if (R > 0 && cap > 0) {
+        e = device_scan(LoadTilesOfSorted{P.ntiles, sorted_rec}, StoreArray{pair_off}, vis_cnt, partials, s);
+        if (e != hipSuccess) return e;
+        emit_pairs_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(B.hdr, sorted_rec, pair_off, P.bbox,
+                                                                     P.views, (uint32_t)n, tile_w, tile_h,
+                                                                     pkeys_a, emit_vals);
+        // 3. stable sort by global tile id
+        bool pairs_in_b = false;
+        const Count pair_cnt{&B.hdr->n_pairs, cap};
+        e = radix_sort(pkeys_a, emit_vals, pkeys_b, other_vals, pair_cnt, 0, tile_bits, hist, partials, s,
+                       &pairs_in_b);
+        if (e != hipSuccess) return e;
+        const uint32_t *skeys = pairs_in_b ? pkeys_b : pkeys_a;
+        fill_u32_kernel<<<(unsigned)ceil_div(2 * n_tiles, 256), 256, 0, s>>>((uint32_t *)B.tile_range,
+                                                                             2 * n_tiles, 0u);
+        tile_ranges_kernel<<<(unsigned)ceil_div(cap, 256), 256, 0, s>>>(B.hdr, skeys, B.tile_range);
+    } else {
+        fill_u32_kernel<<<(unsigned)ceil_div(2 * n_tiles, 256), 256, 0, s>>>((uint32_t *)B.tile_range,
+                                                                             2 * n_tiles, 0u);
+    }
+    // 4. work order: heaviest tiles first (two 8-bit passes, result back in the a buffers)
+    if (n_tiles > 0) {
+        tile_cost_keys_kernel<<<(unsigned)ceil_div(n_tiles, 256), 256, 0, s>>>(B.tile_range, n_tiles, tkeys_a,
+                                                                               B.tile_order);
+        bool in_b = false;
+        e = radix_sort(tkeys_a, B.tile_order, tkeys_b, tvals_tmp, Count{nullptr, n_tiles}, 0, 16, hist,
+                       partials, s, &in_b);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dbs

@@ -1,0 +1,312 @@
+"""Rasterizer front end over the C ABI of libdbs.
+
+PyTorch provides device memory and streams; every step of the path runs in
+the library's HIP kernels.
+
+    rast = Rasterizer(cameras, n_splats, n_lobes)
+    image, T, last = rast.forward(params)            # eager, sizes bins exactly
+    rast.backward(params, dL_dimage, T, last, grads) # grads accumulate (+=)
+
+`render(params, rast)` wraps the two in a torch.autograd.Function.
+`TrainStep` captures preprocess -> bin/sort -> forward -> L1 loss -> backward
+for a fixed scene size in one HIP graph (the batched multi-view step).
+
+Parameters are a dict of contiguous float32 CUDA tensors (names as in
+`_lib.PARAMS`); cameras are the dicts of `scenes.camera`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PARAMS, check
+
+
+@dataclass
+class RasterConfig:
+    tile_w: int = 16
+    tile_h: int = 16
+    batch: int = 256
+    t_eps: float = 1e-4
+    alpha_max: float = 0.99
+    persistent: bool = True
+
+    def to_c(self) -> _lib.RasterCfg:
+        return _lib.RasterCfg(self.tile_w, self.tile_h, self.batch, self.t_eps, self.alpha_max,
+                              _lib.FLAG_PERSISTENT if self.persistent else 0)
+
+
+def make_cameras(cams) -> C.Array:
+    arr = (_lib.Camera * len(cams))()
+    for k, c in enumerate(cams):
+        vm = np.asarray(c["viewmat"], np.float32).reshape(12)
+        bg = np.asarray(c.get("background", (0, 0, 0)), np.float32).reshape(3)
+        arr[k] = _lib.Camera((C.c_float * 12)(*vm), c["fx"], c["fy"], c["cx"], c["cy"], int(c["width"]),
+                             int(c["height"]), c["near"], (C.c_float * 3)(*bg))
+    return arr
+
+
+def to_device(scene: dict, device="cuda") -> dict:
+    """numpy scene -> dict of contiguous float32 tensors on `device`."""
+    return {k: torch.as_tensor(np.ascontiguousarray(scene[k], np.float32), device=device).contiguous()
+            for k in PARAMS}
+
+
+def _splats_c(params: dict, n: int, m: int) -> _lib.Splats:
+    ptrs = []
+    for k in PARAMS:
+        t = params[k]
+        if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"{k} must be a contiguous float32 CUDA tensor")
+        ptrs.append(t.data_ptr() if t.numel() > 0 else None)
+    return _lib.Splats(*ptrs, n, m)
+
+
+def _grads_c(grads: dict) -> _lib.Grads:
+    return _lib.Grads(*[grads[k].data_ptr() if grads[k].numel() > 0 else None for k in PARAMS])
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Rasterizer:
+    """Buffers and calls for one set of views over a scene of n splats with m
+    lobes.  One forward/backward pair at a time: forward() leaves the state
+    backward() consumes."""
+
+    def __init__(self, cams, n: int, m: int, cfg: RasterConfig | None = None, device="cuda",
+                 pair_capacity: int = 0, headroom: float = 1.0):
+        self.lib = _lib.load()
+        self.cams = list(cams)
+        self.cams_c = make_cameras(self.cams)
+        self.V = len(self.cams)
+        self.n, self.m = int(n), int(m)
+        self.cfg = cfg or RasterConfig()
+        self.cfg_c = self.cfg.to_c()
+        self.device = torch.device(device)
+        self.headroom = headroom
+        self.sizes = [(int(c["height"]), int(c["width"])) for c in self.cams]
+        self.pix_off = np.concatenate([[0], np.cumsum([h * w for h, w in self.sizes])]).astype(np.int64)
+        self.n_pixels = int(self.pix_off[-1])
+        pb = self.lib.dbs_projected_bytes(self.n, self.V)
+        if pb == 0:
+            raise ValueError("invalid splat or view count")
+        self.projected = torch.empty(pb, dtype=torch.uint8, device=self.device)
+        self.counts = torch.zeros(2, dtype=torch.int64, device=self.device)
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.capacity = -1
+        self.bins = None
+        self.workspace = None
+        self.ensure_capacity(pair_capacity)
+
+    # ---- buffers ----
+    def ensure_capacity(self, pairs: int):
+        if pairs <= self.capacity:
+            return
+        cap = int(pairs)
+        bb = self.lib.dbs_bins_bytes(cap, self.cams_c, self.V, C.byref(self.cfg_c))
+        wb = self.lib.dbs_workspace_bytes(self.n, self.V, cap, self.cams_c, C.byref(self.cfg_c))
+        if bb == 0 or wb == 0:
+            raise ValueError("invalid camera or raster configuration")
+        self.bins = None
+        self.workspace = None
+        self.bins = torch.empty(bb, dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        self.capacity = cap
+
+    def new_outputs(self):
+        image = torch.empty(3 * self.n_pixels, dtype=torch.float32, device=self.device)
+        final_T = torch.empty(self.n_pixels, dtype=torch.float32, device=self.device)
+        last = torch.empty(self.n_pixels, dtype=torch.int32, device=self.device)
+        return image, final_T, last
+
+    # ---- the four calls ----
+    def preprocess(self, params: dict):
+        sp = _splats_c(params, self.n, self.m)
+        check("dbs_preprocess", self.lib.dbs_preprocess(
+            C.byref(sp), self.cams_c, self.V, C.byref(self.cfg_c), C.c_void_p(self.projected.data_ptr()),
+            self.projected.numel(), C.c_void_p(self.counts.data_ptr()), _stream()))
+
+    def bin_sort(self):
+        check("dbs_bin_sort", self.lib.dbs_bin_sort(
+            C.c_void_p(self.projected.data_ptr()), self.cams_c, self.V, C.byref(self.cfg_c), self.n,
+            self.capacity, C.c_void_p(self.bins.data_ptr()), self.bins.numel(),
+            C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+            C.c_void_p(self.overflow.data_ptr()), _stream()))
+
+    def render_fwd(self, image, final_T, last):
+        check("dbs_render_fwd", self.lib.dbs_render_fwd(
+            C.c_void_p(self.projected.data_ptr()), C.c_void_p(self.bins.data_ptr()), self.cams_c, self.V,
+            C.byref(self.cfg_c), self.n, C.c_void_p(image.data_ptr()), C.c_void_p(final_T.data_ptr()),
+            C.c_void_p(last.data_ptr()), _stream()))
+
+    def render_bwd(self, params: dict, dL_dimage, final_T, last, grads: dict):
+        sp = _splats_c(params, self.n, self.m)
+        gr = _grads_c(grads)
+        check("dbs_render_bwd", self.lib.dbs_render_bwd(
+            C.byref(sp), C.c_void_p(self.projected.data_ptr()), C.c_void_p(self.bins.data_ptr()),
+            self.cams_c, self.V, C.byref(self.cfg_c), C.c_void_p(final_T.data_ptr()),
+            C.c_void_p(last.data_ptr()), C.c_void_p(dL_dimage.data_ptr()), C.byref(gr),
+            C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(), _stream()))
+
+    # ---- eager helpers ----
+    def forward(self, params: dict, outputs=None):
+        """preprocess, size the bins from the exact pair count (one host sync),
+        bin/sort, composite.  Returns (image [3*sum HW], final_T, last_index)."""
+        self.preprocess(params)
+        k = int(self.counts[1].item())
+        self.ensure_capacity(int(k * self.headroom) if self.headroom > 1 else k)
+        self.bin_sort()
+        image, final_T, last = outputs or self.new_outputs()
+        self.render_fwd(image, final_T, last)
+        return image, final_T, last
+
+    def backward(self, params: dict, dL_dimage, final_T, last, grads: dict):
+        self.render_bwd(params, dL_dimage.contiguous(), final_T, last, grads)
+        return grads
+
+    def l1_loss(self, image, target, scale: float, dL_dimage, loss=None):
+        check("dbs_l1_loss", self.lib.dbs_l1_loss(
+            C.c_void_p(image.data_ptr()), C.c_void_p(target.data_ptr()), image.numel(), float(scale),
+            C.c_void_p(dL_dimage.data_ptr()), C.c_void_p(loss.data_ptr()) if loss is not None else None,
+            _stream()))
+
+    # ---- views of the flat buffers ----
+    def split_image(self, image):
+        """flat planar image -> list of [3, H, W] views."""
+        return [image[3 * int(self.pix_off[v]):3 * int(self.pix_off[v + 1])].view(3, h, w)
+                for v, (h, w) in enumerate(self.sizes)]
+
+    def split_pixels(self, flat):
+        """flat per-pixel buffer -> list of [H, W] views."""
+        return [flat[int(self.pix_off[v]):int(self.pix_off[v + 1])].view(h, w)
+                for v, (h, w) in enumerate(self.sizes)]
+
+    # ---- introspection ----
+    def records(self) -> dict:
+        """Per-record arrays (record r = v n + i) viewed from `projected`."""
+        ptrs = [C.c_void_p() for _ in range(7)]
+        check("dbs_projected_layout", self.lib.dbs_projected_layout(
+            C.c_void_p(self.projected.data_ptr()), self.n, self.V, *[C.byref(p) for p in ptrs]))
+        base = self.projected.data_ptr()
+        R = self.n * self.V
+
+        def sl(p, nbytes, dtype, shape):
+            off = (p.value or base) - base
+            return self.projected[off:off + nbytes].view(dtype).view(*shape)
+
+        return dict(centre=sl(ptrs[0], 16 * R, torch.float32, (R, 4)),
+                    conic=sl(ptrs[1], 16 * R, torch.float32, (R, 4)),
+                    color=sl(ptrs[2], 16 * R, torch.float32, (R, 4)),
+                    bbox=sl(ptrs[3], 8 * R, torch.int16, (R, 4)),
+                    depth=sl(ptrs[4], 4 * R, torch.int32, (R,)),
+                    ntiles=sl(ptrs[5], 4 * R, torch.int32, (R,)),
+                    counts=sl(ptrs[6], 16, torch.int64, (2,)))
+
+    def bins_arrays(self) -> dict:
+        ptrs = [C.c_void_p() for _ in range(3)]
+        nt = C.c_int64()
+        check("dbs_bins_layout", self.lib.dbs_bins_layout(
+            C.c_void_p(self.bins.data_ptr()), self.capacity, self.cams_c, self.V, C.byref(self.cfg_c),
+            *[C.byref(p) for p in ptrs], C.byref(nt)))
+        base = self.bins.data_ptr()
+        T = nt.value
+
+        def sl(p, nbytes, dtype, shape):
+            off = (p.value or base) - base
+            return self.bins[off:off + nbytes].view(dtype).view(*shape)
+
+        return dict(pair_rec=sl(ptrs[0], 4 * self.capacity, torch.int32, (self.capacity,)),
+                    tile_range=sl(ptrs[1], 8 * T, torch.int32, (T, 2)),
+                    tile_order=sl(ptrs[2], 4 * T, torch.int32, (T,)), n_tiles=T)
+
+    def tile_offsets(self):
+        """First global tile id of every view (host)."""
+        tw, th = self.cfg.tile_w, self.cfg.tile_h
+        nt = [((w + tw - 1) // tw) * ((h + th - 1) // th) for h, w in self.sizes]
+        return np.concatenate([[0], np.cumsum(nt)]).astype(np.int64)
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rast: Rasterizer, *tensors):
+        params = dict(zip(PARAMS, tensors))
+        image, final_T, last = rast.forward(params)
+        ctx.rast = rast
+        ctx.save_for_backward(*tensors, final_T, last)
+        ctx.mark_non_differentiable(final_T, last)
+        return image, final_T, last
+
+    @staticmethod
+    def backward(ctx, g_image, g_T, g_last):
+        saved = ctx.saved_tensors
+        params = dict(zip(PARAMS, saved[:len(PARAMS)]))
+        final_T, last = saved[len(PARAMS)], saved[len(PARAMS) + 1]
+        grads = {k: torch.zeros_like(params[k]) for k in PARAMS}
+        ctx.rast.backward(params, g_image.contiguous(), final_T, last, grads)
+        return (None, *[grads[k] for k in PARAMS])
+
+
+def render(params: dict, rast: Rasterizer):
+    """Differentiable render of all views: (image [3*sum HW], final_T, last_index)."""
+    return _RenderFn.apply(rast, *[params[k] for k in PARAMS])
+
+
+class TrainStep:
+    """One fixed-size training step (forward, L1 loss to a target, backward)
+    over all views, captured once in a HIP graph and replayed.
+
+    The pair capacity is fixed at capture time from an eager run times
+    `headroom`; a replay whose pair count exceeds it sets `overflow`, leaves
+    every tile list empty, and `replay()` reports it so the caller can
+    rebuild with a larger capacity."""
+
+    def __init__(self, rast: Rasterizer, params: dict, target, headroom: float = 1.1, use_graph=True):
+        self.rast = rast
+        self.params = params
+        self.target = target
+        self.scale = 1.0 / float(target.numel())
+        self.image, self.final_T, self.last = rast.new_outputs()
+        self.dL = torch.empty_like(self.image)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=rast.device)
+        self.grads = {k: torch.zeros_like(params[k]) for k in PARAMS}
+        # eager sizing run
+        rast.preprocess(params)
+        k = int(rast.counts[1].item())
+        rast.ensure_capacity(int(k * headroom) + 1024)
+        self.graph = None
+        if use_graph:
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                self._body()  # warm up (first-use host work outside the capture)
+            torch.cuda.current_stream().wait_stream(s)
+            torch.cuda.synchronize()
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph):
+                self._body()
+            torch.cuda.synchronize()
+
+    def _body(self):
+        r = self.rast
+        r.preprocess(self.params)
+        r.bin_sort()
+        r.render_fwd(self.image, self.final_T, self.last)
+        r.l1_loss(self.image, self.target, self.scale, self.dL, self.loss)
+        for g in self.grads.values():
+            g.zero_()
+        r.render_bwd(self.params, self.dL, self.final_T, self.last, self.grads)
+
+    def run(self):
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self._body()
+
+    def overflowed(self) -> bool:
+        return bool(self.rast.overflow.item())

@@ -1,0 +1,293 @@
+"""HIP path vs the CPU FP64 oracle: projection, binning (bit-exact), forward
+images (1e-5), gradients, edge cases.  Needs an MI355X."""
+import numpy as np
+import pytest
+
+from paper_2501_18630_amd import scenes
+from gpu_helpers import (AMAX, TEPS, PARAMS, assert_grads_close, assert_image_close, gpu_render, hw3,
+                         oracle_view)
+
+pytestmark = pytest.mark.gpu
+
+
+def cfg(tw=16, th=16, batch=256, persistent=True):
+    from paper_2501_18630_amd.renderer import RasterConfig
+    return RasterConfig(tile_w=tw, tile_h=th, batch=batch, persistent=persistent)
+
+
+def tiny_scene(n, seed, m=2, lo=(-1.2, -1.2, 1.0), hi=(1.2, 1.2, 5.0), log_scale=(np.log(0.03), np.log(0.4))):
+    return scenes.uniform_box_scene(n, lo, hi, m=m, seed=seed, log_scale=log_scale)
+
+
+# ---------------------------------------------------------------- projection
+
+@pytest.mark.parametrize("which", ["c0", "tiny", "c1"])
+def test_preprocess_matches_oracle(oracle, which):
+    if which == "c0":
+        s, cams = scenes.config0()
+    elif which == "tiny":
+        s, cams = tiny_scene(300, 3), [scenes.look_at_camera([1.0, -2.0, -6.0], 53, 41)]
+    else:
+        s, cams = scenes.config1()
+    out = gpu_render(s, cams)
+    rec = {k: v.cpu().numpy() for k, v in out["rast"].records().items()}
+    n = s["means"].shape[0]
+    p = oracle.project(s, cams[0])
+    nt = rec["ntiles"][:n]
+    bb = p["bbox"]
+    live = (p["valid"] == 1) & (bb[:, 0] <= bb[:, 1]) & (bb[:, 2] <= bb[:, 3])
+    # visibility, boxes and depth keys: bit-exact
+    np.testing.assert_array_equal(nt > 0, live)
+    np.testing.assert_array_equal(rec["bbox"][:n][live].astype(np.int32), bb[live])
+    np.testing.assert_array_equal(rec["depth"][:n].view(np.uint32)[p["valid"] == 1],
+                                  p["depth_key"][p["valid"] == 1])
+    tw = th = 16
+    ref_nt = (bb[:, 1] // tw - bb[:, 0] // tw + 1) * (bb[:, 3] // th - bb[:, 2] // th + 1)
+    np.testing.assert_array_equal(nt[live], ref_nt[live])
+    # centre (hi + lo) to FP64 rounding, conic/opacity/beta to FP32 rounding, colour to 1e-6
+    c = rec["centre"][:n][live].astype(np.float64)
+    np.testing.assert_allclose(c[:, :2] + c[:, 2:], p["mean2d"][live], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(rec["conic"][:n][live][:, :3], p["conic"][live], rtol=2e-6, atol=1e-9)
+    np.testing.assert_allclose(rec["conic"][:n][live][:, 3], s["opacities"][live], rtol=0, atol=0)
+    np.testing.assert_allclose(rec["color"][:n][live][:, 3], p["beta"][live], rtol=1e-6)
+    np.testing.assert_allclose(rec["color"][:n][live][:, :3], p["color"][live], rtol=0, atol=2e-6)
+    assert rec["counts"][0] == live.sum() and rec["counts"][1] == ref_nt[live].sum()
+
+
+# ---------------------------------------------------------------- binning
+
+def _check_bins(oracle, out, cams, n, bbox_src, tw, th):
+    rast = out["rast"]
+    b = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in rast.bins_arrays().items()}
+    toff = rast.tile_offsets()
+    rec = {k: v.cpu().numpy() for k, v in rast.records().items()}
+    total = 0
+    for v, cam in enumerate(cams):
+        sl = slice(v * n, (v + 1) * n)
+        if bbox_src == "gpu":
+            valid = (rec["ntiles"][sl] > 0).astype(np.int32)
+            bbox = rec["bbox"][sl].astype(np.int32)
+            dk = rec["depth"][sl].view(np.uint32)
+        else:
+            p = oracle.project(out["scene"], cam)
+            valid, bbox, dk = p["valid"], p["bbox"], p["depth_key"]
+        start, ids = oracle.bin_pairs(valid, bbox, dk, cam["width"], cam["height"], tw, th)
+        nt = start.size - 1
+        rng = b["tile_range"][toff[v]:toff[v] + nt]
+        for t in range(nt):
+            s0, s1 = int(rng[t, 0]), int(rng[t, 1])
+            got = b["pair_rec"][s0:s1].astype(np.int64) - v * n
+            ref = ids[start[t]:start[t + 1]]
+            if got.size != ref.size or not np.array_equal(got, ref):
+                raise AssertionError(f"view {v} tile {t}: {got[:8]} vs {ref[:8]}")
+        total += ids.size
+    assert total == int(rec["counts"][1])
+    # work order is a permutation, heaviest first
+    order = b["tile_order"].astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(b["n_tiles"]))
+    cnt = np.minimum(b["tile_range"][:, 1] - b["tile_range"][:, 0], 0xFFFF)[order]
+    assert np.all(np.diff(cnt) <= 0)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8), (16, 8), (32, 16)])
+def test_binning_bit_exact_tiny(oracle, tile):
+    s = tiny_scene(400, 5)
+    cams = [scenes.look_at_camera([0.5, 0.3, -5.0], 75, 53), scenes.camera(37, 29, f=30.0)]
+    out = gpu_render(s, cams, cfg(*tile))
+    out["scene"] = s
+    _check_bins(oracle, out, cams, 400, "gpu", *tile)
+    _check_bins(oracle, out, cams, 400, "oracle", *tile)
+
+
+def test_binning_bit_exact_c1(oracle):
+    s, cams = scenes.config1()
+    out = gpu_render(s, cams)
+    out["scene"] = s
+    _check_bins(oracle, out, cams, s["means"].shape[0], "gpu", 16, 16)
+    _check_bins(oracle, out, cams, s["means"].shape[0], "oracle", 16, 16)
+
+
+# ---------------------------------------------------------------- forward
+
+def test_forward_config0(oracle):
+    s, cams = scenes.config0()
+    out = gpu_render(s, cams)
+    ref = oracle_view(oracle, s, cams[0])
+    err = assert_image_close(hw3(out["images"][0]), ref["rgb"], ref["T"], ref["T_prev"])
+    np.testing.assert_allclose(out["T"][0].reshape(-1), ref["T"], atol=1e-5)
+    np.testing.assert_array_equal(out["last_id"][0].reshape(-1), ref["last"])
+    assert err < 1e-5
+
+
+def test_forward_config1_crop(oracle):
+    s, cams = scenes.config1()
+    out = gpu_render(s, cams)
+    x0, y0 = 480, 352
+    pix = oracle.crop_pixels(x0, y0, 64, 64)
+    ref = oracle_view(oracle, s, cams[0], pix)
+    gpu = hw3(out["images"][0][:, y0:y0 + 64, x0:x0 + 64])
+    assert_image_close(gpu, ref["rgb"], ref["T"], ref["T_prev"])
+    ok = np.abs(ref["T"] / float(TEPS) - 1) > 1e-5
+    np.testing.assert_array_equal(out["last_id"][0][y0:y0 + 64, x0:x0 + 64].reshape(-1)[ok], ref["last"][ok])
+
+
+@pytest.mark.parametrize("tile,batch,persistent", [((16, 16), 64, True), ((8, 8), 128, False),
+                                                   ((32, 8), 256, True), ((32, 16), 64, False),
+                                                   ((16, 8), 256, False)])
+def test_forward_tiles_and_ragged_views(oracle, tile, batch, persistent):
+    s = tiny_scene(500, 7, m=3)
+    s["opacities"][:] = np.clip(s["opacities"] * 1.6, 0, 1)    # some clamped alphas
+    cams = [scenes.camera(37, 29, f=30.0, background=(0.2, 0.4, 0.6)),
+            scenes.look_at_camera([2.0, 1.0, -5.0], 50, 33, background=(1.0, 0.0, 0.5))]
+    out = gpu_render(s, cams, cfg(*tile, batch, persistent))
+    for v, cam in enumerate(cams):
+        ref = oracle_view(oracle, s, cam)
+        assert_image_close(hw3(out["images"][v]), ref["rgb"], ref["T"], ref["T_prev"])
+
+
+def test_forward_edge_cases(oracle):
+    # empty scene: background everywhere, T = 1, last = -1
+    e = tiny_scene(0, 1)
+    out = gpu_render(e, [scenes.camera(20, 10, background=(0.1, 0.2, 0.3))])
+    np.testing.assert_array_equal(out["images"][0], np.broadcast_to(
+        np.float32([0.1, 0.2, 0.3])[:, None, None], (3, 10, 20)))
+    assert np.all(out["T"][0] == 1.0) and np.all(out["last"][0] == -1)
+    # everything behind the camera or on the near plane
+    b = tiny_scene(50, 2, lo=(-1, -1, -5), hi=(1, 1, 0.2))
+    out = gpu_render(b, [scenes.camera(16, 16)])
+    assert np.all(out["T"][0] == 1.0)
+    # 1x1 image, a splat covering far more than the image, M = 0 and M = 8
+    for m in (0, 8):
+        g = tiny_scene(20, 9, m=m)
+        g["scales"][0] = [50.0, 40.0, 30.0]
+        for cam in (scenes.camera(1, 1, f=1.0), scenes.camera(33, 17, f=20.0)):
+            out = gpu_render(g, [cam])
+            ref = oracle_view(oracle, g, cam)
+            assert_image_close(hw3(out["images"][0]), ref["rgb"], ref["T"], ref["T_prev"])
+
+
+def test_forward_deterministic_and_batched_equals_per_view(oracle):
+    s = tiny_scene(800, 11, m=2)
+    cams = [scenes.look_at_camera(p, w, h) for p, (w, h) in
+            zip([[0, 0, -6.0], [3.0, 1.0, -5.0], [-2.0, 2.0, -4.0]], [(64, 48), (40, 40), (33, 65)])]
+    a = gpu_render(s, cams)
+    b = gpu_render(s, cams)
+    for v in range(3):
+        np.testing.assert_array_equal(a["images"][v], b["images"][v])
+        single = gpu_render(s, [cams[v]])
+        np.testing.assert_array_equal(a["images"][v], single["images"][0])
+        np.testing.assert_array_equal(a["T"][v], single["T"][0])
+        np.testing.assert_array_equal(a["last_id"][v], single["last_id"][0])
+    np_ = gpu_render(s, cams, cfg(persistent=False))
+    for v in range(3):
+        np.testing.assert_array_equal(a["images"][v], np_["images"][v])
+
+
+# ---------------------------------------------------------------- backward
+
+def _dl(cams, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((3, c["height"], c["width"])).astype(np.float32) for c in cams]
+
+
+@pytest.mark.parametrize("which", ["tiny", "c0", "multiview"])
+def test_backward_matches_oracle(oracle, which):
+    if which == "c0":
+        s, cams = scenes.config0()
+    elif which == "tiny":
+        s, cams = tiny_scene(60, 13, m=2), [scenes.look_at_camera([1.0, 0.5, -5.0], 40, 30,
+                                                                  background=(0.3, 0.2, 0.1))]
+    else:
+        s = tiny_scene(120, 17, m=4)
+        cams = [scenes.look_at_camera(p, 36, 28) for p in ([0, 0, -6.0], [2.5, -1.0, -5.0], [-3.0, 1.0, -4.0])]
+    dl = _dl(cams, 42)
+    out = gpu_render(s, cams, grads_from=dl)
+    g_ref = {k: 0.0 for k in PARAMS}
+    a_ref = {k: 0.0 for k in PARAMS}
+    for v, cam in enumerate(cams):
+        g, a = oracle.render_bwd(s, cam, float(AMAX), float(TEPS), hw3(dl[v]), want_abs=True)
+        for k in PARAMS:
+            g_ref[k] = g_ref[k] + g[k]
+            a_ref[k] = a_ref[k] + a[k]
+    assert_grads_close(out["grads"], g_ref, a_ref)
+
+
+def test_backward_config1_crop_and_finite_differences(oracle):
+    s, cams = scenes.config1()
+    cam = cams[0]
+    x0, y0, w = 480, 352, 64
+    rng = np.random.default_rng(7)
+    dl_crop = rng.standard_normal((3, w, w)).astype(np.float32)
+    dl = np.zeros((3, cam["height"], cam["width"]), np.float32)
+    dl[:, y0:y0 + w, x0:x0 + w] = dl_crop
+    out = gpu_render(s, cams, grads_from=[dl])
+    pix = oracle.crop_pixels(x0, y0, w, w)
+    # only splats whose box meets the crop can change it
+    p = oracle.project(s, cam)
+    bb = p["bbox"]
+    near = np.where((p["valid"] == 1) & (bb[:, 0] <= x0 + w - 1) & (bb[:, 1] >= x0) & (bb[:, 2] <= y0 + w - 1)
+                    & (bb[:, 3] >= y0) & (bb[:, 0] <= bb[:, 1]) & (bb[:, 2] <= bb[:, 3]))[0]
+    sub = scenes.subset(s, near)
+    g, a = oracle.render_bwd(sub, cam, float(AMAX), float(TEPS), hw3(dl_crop), pixels=pix, want_abs=True)
+    g_gpu = {k: out["grads"][k][near] for k in PARAMS}
+    far = np.setdiff1d(np.arange(s["means"].shape[0]), near)
+    for k in PARAMS:
+        assert np.all(out["grads"][k][far] == 0.0), k
+    assert_grads_close(g_gpu, g, a)
+    # 8 random parameters of splats touching the crop against central differences
+    # of the FP64 oracle's crop loss
+    sub64 = {k: v.astype(np.float64) for k, v in sub.items()}
+    w_flat = hw3(dl_crop).astype(np.float64)
+
+    def loss(sc):
+        return float((oracle.render(sc, cam, float(AMAX), float(TEPS), pixels=pix)["rgb"] * w_flat).sum())
+
+    pick = np.random.default_rng(4)
+    checked = 0
+    while checked < 8:
+        k = PARAMS[pick.integers(0, len(PARAMS))]
+        if sub64[k].size == 0:
+            continue
+        j = int(pick.integers(0, sub64[k].size))
+        flat = sub64[k].reshape(-1)
+        x = flat[j]
+        h = 1e-6 * max(1.0, abs(x))
+        flat[j] = x + h
+        lp = loss(sub64)
+        flat[j] = x - h
+        lm = loss(sub64)
+        flat[j] = x
+        fd = (lp - lm) / (2 * h)
+        an = g_gpu[k].reshape(-1)[j]
+        assert abs(an - fd) <= 1e-3 * abs(fd) + 1e-5 * a[k].reshape(-1)[j] + 1e-9, (k, j, an, fd)
+        checked += 1
+
+
+# ---------------------------------------------------------------- errors
+
+def test_overflow_flag_and_invalid_arguments():
+    import torch
+    from paper_2501_18630_amd import renderer, _lib
+    s, cams = scenes.config0()
+    rast = renderer.Rasterizer(cams, 256, 2)
+    params = renderer.to_device(s)
+    rast.preprocess(params)
+    k = int(rast.counts[1].item())
+    assert k > 10
+    rast.ensure_capacity(k // 2)
+    rast.bin_sort()
+    img, T, last = rast.new_outputs()
+    rast.render_fwd(img, T, last)
+    torch.cuda.synchronize()
+    assert int(rast.overflow.item()) == 1
+    assert torch.all(T == 1.0) and torch.all(img == 0.0)
+    rast.ensure_capacity(k)
+    rast.bin_sort()
+    rast.render_fwd(img, T, last)
+    assert int(rast.overflow.item()) == 0 and float(T.min()) < 1.0
+    with pytest.raises(_lib.DbsError):
+        renderer.Rasterizer(cams, 256, 2, renderer.RasterConfig(tile_w=12)).preprocess(params)
+    bad = dict(cams[0])
+    bad["width"] = 0
+    with pytest.raises(ValueError):
+        renderer.Rasterizer([bad], 256, 2)
