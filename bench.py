@@ -1,0 +1,234 @@
+"""Benchmark: fwd+bwd Mpix/s of the Beta-splatting rasterizer on one MI355X,
+batched multi-view (one call per stage, replayed from a HIP graph) vs per-view
+(the same calls once per view, eager).
+
+    python bench.py [--steps K] [--warmup W] [--config 3] [--no-cpu-baseline]
+
+A step is one training iteration of the whole hot path over every view:
+preprocess -> bin/sort -> forward -> L1 loss gradient -> backward (gradients
+of every splat parameter).  Inputs are resident in HBM before timing starts.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
+
+# Algorithmic FP32 operations (an FMA counts 2, a transcendental 1) per
+# (pixel, pair), counted from the arithmetic the method needs:
+#   support test r^2 = d^T A d of every evaluated pair ............... 9
+#   forward compositing of a pair with r^2 < 1 (Eq. 6) ............... 15
+#   reverse pass of a pair with r^2 < 1, including its share of the
+#   per-splat sums over pixels (10 values) ........................... 68
+FLOP_TEST = 9
+FLOP_FWD_CONTRIB = 15
+FLOP_BWD_CONTRIB = 68
+
+
+def step_bytes(q_floats: int, n: int, visible: int, pairs: int, pixels: int) -> int:
+    """Algorithmic HBM bytes of one training step (batched): parameters read
+    twice and gradients written once (12 Q N), 128 B per visible record
+    (projection record, depth, count written; read by the sort; screen-space
+    gradient written and read), 124 B per (tile, splat) pair (emission, one
+    stable sort pass, raster reads in both directions), 40 B per pixel (image,
+    T, last index, dL/dimage)."""
+    return 12 * q_floats * n + 128 * visible + 124 * pairs + 40 * pixels
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-pixels", type=int, default=3072)
+    return ap.parse_args()
+
+
+def timed(fn, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def stage_times(rast, step, steps):
+    """Average ms of each stage of the batched step, HIP events recorded on
+    torch's current stream, which is the stream the library launches on."""
+    import torch
+    names = ("preprocess", "bin_sort", "raster_fwd", "l1_loss", "raster_bwd", "project_bwd")
+    acc = {k: 0.0 for k in names}
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        for g in step.grads.values():
+            g.zero_()
+        ev[0].record()
+        rast.preprocess(step.params)
+        ev[1].record()
+        rast.bin_sort()
+        ev[2].record()
+        rast.render_fwd(step.image, step.final_T, step.last)
+        ev[3].record()
+        rast.l1_loss(step.image, step.target, step.scale, step.dL, step.loss)
+        ev[4].record()
+        rast.raster_bwd(step.dL, step.final_T, step.last)
+        ev[5].record()
+        rast.project_bwd(step.params, step.grads)
+        ev[6].record()
+        torch.cuda.synchronize()
+        for k, name in enumerate(names):
+            acc[name] += ev[k].elapsed_time(ev[k + 1])
+    return {k: v / steps for k, v in acc.items()}
+
+
+def work_counts(rast, step):
+    """Pair counts and evaluated / contributing (pixel, pair) counts of the
+    last step, from the library's counting pass (outside the timed region)."""
+    counts = {"pairs": int(rast.counts[1].item()), "visible": int(rast.counts[0].item())}
+    counts.update(rast.stats(step.final_T, step.last))
+    return counts
+
+
+def cpu_baseline(scene, cams, n_pixels: int, seed: int = 5):
+    """The oracle, as it is, on a bounded sample: fwd + bwd of `n_pixels`
+    random pixels of the first view (every splat of the scene is projected
+    and depth-sorted for that view, then each sampled pixel is composited by
+    brute force over all of them)."""
+    import oracle
+    cam = cams[0]
+    rng = np.random.default_rng(seed)
+    pix = np.stack([rng.integers(0, cam["width"], n_pixels), rng.integers(0, cam["height"], n_pixels)], 1)
+    dl = rng.standard_normal((n_pixels, 3))
+    amax, teps = float(np.float32(0.99)), float(np.float32(1e-4))
+    t0 = time.perf_counter()
+    oracle.render(scene, cam, amax, teps, pixels=pix)
+    oracle.render_bwd(scene, cam, amax, teps, dl, pixels=pix)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_pixels / dt / 1e6, "unit": "Mpix/s", "cores": cores, "kind": "oracle",
+            "sample": f"fwd+bwd of {n_pixels} random pixels of view 0 ({cam['width']}x{cam['height']}) over "
+                      f"all {scene['means'].shape[0]} splats, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU would shard views, see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    from paper_2501_18630_amd import renderer, scenes
+
+    tw, th = (int(x) for x in args.tile.split("x"))
+    cfg = renderer.RasterConfig(tile_w=tw, tile_h=th, batch=args.batch)
+    t0 = time.perf_counter()
+    scene, cams = scenes.CONFIGS[args.config]()
+    n, m = scene["means"].shape[0], scene["lobe_betas"].shape[1]
+    log(f"scene: config {args.config}, {n} splats, {m} lobes, {len(cams)} views "
+        f"({time.perf_counter() - t0:.1f} s)")
+    params = renderer.to_device(scene)
+    targets = [scenes.target_image(c["height"], c["width"], seed=1 + v) for v, c in enumerate(cams)]
+    target_flat = torch.as_tensor(np.concatenate([t.reshape(-1) for t in targets])).cuda()
+    X = sum(c["width"] * c["height"] for c in cams)
+
+    rast = renderer.Rasterizer(cams, n, m, cfg)
+    step = renderer.TrainStep(rast, params, target_flat, headroom=1.1, use_graph=True)
+    for _ in range(args.warmup):
+        step.run()
+    t_batched = timed(step.run, args.steps)
+    assert not step.overflowed()
+    log(f"batched: {t_batched * 1e3:.3f} ms/step")
+
+    per_view = None
+    if not args.no_per_view:
+        steps_v = []
+        off = 0
+        for v, c in enumerate(cams):
+            npx = c["width"] * c["height"]
+            r = renderer.Rasterizer([c], n, m, cfg)
+            steps_v.append(renderer.TrainStep(r, params, target_flat[3 * off:3 * (off + npx)], headroom=1.1,
+                                              use_graph=False))
+            off += npx
+
+        def run_views():
+            for s in steps_v:
+                s.run()
+
+        for _ in range(args.warmup):
+            run_views()
+        t_pv = timed(run_views, args.steps)
+        per_view = X / t_pv / 1e6
+        log(f"per-view: {t_pv * 1e3:.3f} ms/step")
+        del steps_v
+
+    st = stage_times(rast, step, max(3, args.steps // 2))
+    log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
+    wc = work_counts(rast, step)
+    log(f"work: {wc}")
+
+    mpix = X / t_batched / 1e6
+    q_floats = 15 + 6 * m
+    sb = step_bytes(q_floats, n, wc["visible"], wc["pairs"], X)
+    # dominant kernel: the raster reverse pass; ALU-bound (support tests plus
+    # the reverse arithmetic of contributing pairs), priced against FP32 peak
+    bwd_flops = wc["bwd_evaluated"] * FLOP_TEST + wc["contributing"] * FLOP_BWD_CONTRIB
+    t_bwd = st["raster_bwd"] * 1e-3
+    achieved = bwd_flops / t_bwd / 1e12
+    fwd_flops = wc["fwd_evaluated"] * FLOP_TEST + wc["contributing"] * FLOP_FWD_CONTRIB
+    result = {
+        "metric": "fwd+bwd Mpix/s, batched vs per-view, 1 MI355X, img err<=1e-5 vs FP64",
+        "value": round(mpix, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_batched * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"config{args.config}: {len(cams)} views (sum {X} px), {n} splats, "
+                               f"{m} lobes, tile {tw}x{th}, batch {args.batch}, batched + hipGraph",
+                   "views": len(cams), "pixels": X, "splats": n, "lobes": m},
+        "per_view_value": round(per_view, 3) if per_view else None,
+        "batched_speedup": round(mpix / per_view, 3) if per_view else None,
+        "roofline": {"kernel": "raster_bwd_kernel", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "flops_per_launch": bwd_flops, "ms_per_launch": round(st["raster_bwd"], 4)},
+        "step_hbm": {"algorithmic_bytes": sb, "achieved_GBs": round(sb / t_batched / 1e9, 1),
+                     "peak_GBs": HBM_PEAK_GBS, "frac": round(sb / t_batched / 1e9 / HBM_PEAK_GBS, 4)},
+        "raster_fwd_tflops": round(fwd_flops / (st["raster_fwd"] * 1e-3) / 1e12, 3),
+        "stage_ms": {k: round(v, 4) for k, v in st.items()},
+        "work": wc,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(scene, cams, args.cpu_sample_pixels)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -118,7 +118,11 @@ void dbs_default_cfg(dbs_raster_cfg *cfg);
 
 /* ---- buffer sizes (bytes) ---------------------------------------------- */
 
-/* `projected`: per (view, splat) records plus the view table and counters. */
+/* `projected`: per (view, splat) records, the view table, counters and the
+ * per-record screen-space gradient accumulator of the reverse pass.  The
+ * buffer must be zero-filled once before its first use; the library keeps
+ * the accumulator zero between calls (dbs_render_bwd clears what it
+ * consumes). */
 size_t dbs_projected_bytes(int64_t n, int32_t n_views);
 
 /* `bins`: sorted tile lists for up to `pair_capacity` (tile, splat) pairs,
@@ -126,7 +130,7 @@ size_t dbs_projected_bytes(int64_t n, int32_t n_views);
 size_t dbs_bins_bytes(int64_t pair_capacity, const dbs_camera *cams /*[host]*/, int32_t n_views,
                       const dbs_raster_cfg *cfg /*[host]*/);
 
-/* `workspace`: scratch for dbs_bin_sort and dbs_render_bwd. */
+/* `workspace`: scratch for dbs_bin_sort. */
 size_t dbs_workspace_bytes(int64_t n, int32_t n_views, int64_t pair_capacity,
                            const dbs_camera *cams /*[host]*/, const dbs_raster_cfg *cfg /*[host]*/);
 
@@ -169,14 +173,43 @@ dbs_status dbs_render_fwd(const void *projected, const void *bins, const dbs_cam
  * layout as image) it ADDS dL/dparameter to *grads for every parameter of
  * Sec. 3.2 Eq. (4) and Sec. 3.3 Eq. (8), including b and b_m through
  * beta = 4 e^b.  Transmittance is recomputed back to front from final_T and
- * last_index; a clamped alpha passes no gradient to o, b or the geometry. */
+ * last_index; a clamped alpha passes no gradient to o, b or the geometry.
+ * `projected` is read and its gradient accumulator used (and left zero); it
+ * may be called again on the same projected/bins with another dL_dimage. */
 dbs_status dbs_render_bwd(const dbs_splats *splats /*[host] struct of device pointers*/,
                           const void *projected, const void *bins,
                           const dbs_camera *cams /*[host]*/, int32_t n_views,
                           const dbs_raster_cfg *cfg /*[host]*/,
                           const float *final_T, const int32_t *last_index, const float *dL_dimage,
-                          dbs_splat_grads *grads /*[host] struct of device pointers*/,
-                          void *workspace, size_t workspace_bytes, void *stream);
+                          dbs_splat_grads *grads /*[host] struct of device pointers*/, void *stream);
+
+/* The two stages of dbs_render_bwd, callable on their own (same arguments):
+ * dbs_raster_bwd walks the tile lists back to front and accumulates, per
+ * record, the gradient of the screen-space quantities of Eq. (5)-(6)
+ * (mu', conic, o, b, colour) inside `projected`; dbs_project_bwd chains them
+ * to the parameters (Sec. 3.2 projection, Sec. 3.3 Eq. 8), ADDS into *grads
+ * and clears the accumulator.  dbs_render_bwd = dbs_raster_bwd, then
+ * dbs_project_bwd. */
+dbs_status dbs_raster_bwd(const void *projected, const void *bins, const dbs_camera *cams /*[host]*/,
+                          int32_t n_views, const dbs_raster_cfg *cfg /*[host]*/, int64_t n,
+                          const float *final_T, const int32_t *last_index, const float *dL_dimage,
+                          void *stream);
+dbs_status dbs_project_bwd(const dbs_splats *splats /*[host] struct of device pointers*/,
+                           const void *projected, const dbs_camera *cams /*[host]*/, int32_t n_views,
+                           const dbs_raster_cfg *cfg /*[host]*/,
+                           dbs_splat_grads *grads /*[host] struct of device pointers*/, void *stream);
+
+/* Work counts of a finished forward (profiling; not for the timed path).
+ * out[0] += (pixel, pair) evaluations of the support test r^2 < 1 that the
+ *           reverse pass makes: for each pixel, the list positions from its
+ *           tile's start to its last_index;
+ * out[1] += those with r^2 < 1 (the pairs composited by Eq. 6);
+ * out[2] += evaluations of the forward: list positions from the start to the
+ *           pixel's last_index, or to the list end if it never stopped.
+ * out: device int64[3], accumulated. */
+dbs_status dbs_render_stats(const void *projected, const void *bins, const dbs_camera *cams /*[host]*/,
+                            int32_t n_views, const dbs_raster_cfg *cfg /*[host]*/, int64_t n,
+                            const float *final_T, const int32_t *last_index, int64_t *out, void *stream);
 
 /* ---- loss glue ----------------------------------------------------------- */
 

@@ -351,18 +351,18 @@ typedef struct {
     double mean2d[2], G[3], opacity, b, color[3];
 } ob_screen_adj;
 
-static void add_grad(double *g, double *a, int64_t idx, double v)
+static void add_grad(double *g, double *unused, int64_t idx, double v)
 {
+    (void)unused;
     g[idx] += v;
-    if (a) a[idx] += fabs(v);
 }
 
 static void chain_one(const ob_splats *s, int64_t i, const ob_camera *cam, const ob_fwd *f,
-                      const ob_screen_adj *sa, ob_grads *g, ob_grads *a)
+                      const ob_screen_adj *sa, ob_grads *g)
 {
     const double *W = cam->R;
     const int m_l = s->m;
-#define AG(field) (a ? a->field : NULL)
+#define AG(field) NULL
 
     add_grad(g->opacities, AG(opacities), i, sa->opacity);
     add_grad(g->betas, AG(betas), i, sa->b);
@@ -477,9 +477,71 @@ static void chain_one(const ob_splats *s, int64_t i, const ob_camera *cam, const
 #undef AG
 }
 
+
+/* Number of parameters of one splat, in the order means(3) scales(3)
+ * quats(4) opacity beta diffuse(3) lobe_angles(2m) lobe_colors(3m)
+ * lobe_betas(m). */
+static int n_params(int m) { return 15 + 6 * m; }
+
+static void splat_params_get(const ob_grads *g, int64_t i, int m, double *out)
+{
+    int k = 0;
+    for (int c = 0; c < 3; ++c) out[k++] = g->means[3 * i + c];
+    for (int c = 0; c < 3; ++c) out[k++] = g->scales[3 * i + c];
+    for (int c = 0; c < 4; ++c) out[k++] = g->quats[4 * i + c];
+    out[k++] = g->opacities[i];
+    out[k++] = g->betas[i];
+    for (int c = 0; c < 3; ++c) out[k++] = g->diffuse[3 * i + c];
+    for (int c = 0; c < 2 * m; ++c) out[k++] = g->lobe_angles[2 * m * i + c];
+    for (int c = 0; c < 3 * m; ++c) out[k++] = g->lobe_colors[3 * m * i + c];
+    for (int c = 0; c < m; ++c) out[k++] = g->lobe_betas[m * i + c];
+}
+
+static void splat_params_add(ob_grads *g, int64_t i, int m, const double *v)
+{
+    int k = 0;
+    for (int c = 0; c < 3; ++c) g->means[3 * i + c] += v[k++];
+    for (int c = 0; c < 3; ++c) g->scales[3 * i + c] += v[k++];
+    for (int c = 0; c < 4; ++c) g->quats[4 * i + c] += v[k++];
+    g->opacities[i] += v[k++];
+    g->betas[i] += v[k++];
+    for (int c = 0; c < 3; ++c) g->diffuse[3 * i + c] += v[k++];
+    for (int c = 0; c < 2 * m; ++c) g->lobe_angles[2 * m * i + c] += v[k++];
+    for (int c = 0; c < 3 * m; ++c) g->lobe_colors[3 * m * i + c] += v[k++];
+    for (int c = 0; c < m; ++c) g->lobe_betas[m * i + c] += v[k++];
+}
+
+/* Jacobian [n_params][10] of splat i's parameter adjoints with respect to its
+ * ten screen-space adjoints (mean2d 2, G 3, opacity, b, colour 3), by running
+ * the (linear) reverse chain on unit vectors.  `scratch` holds zeros for
+ * splat i on entry and on exit. */
+static void splat_jacobian(const ob_splats *s, int64_t i, const ob_camera *cam, const ob_fwd *f,
+                           ob_grads *scratch, double *J)
+{
+    const int q = n_params(s->m);
+    double *col = (double *)malloc(sizeof(double) * (size_t)q);
+    for (int j = 0; j < 10; ++j) {
+        ob_screen_adj e;
+        memset(&e, 0, sizeof(e));
+        ((double *)&e)[j] = 1.0;
+        chain_one(s, i, cam, f, &e, scratch);
+        splat_params_get(scratch, i, s->m, col);
+        for (int p = 0; p < q; ++p) {
+            J[p * 10 + j] = col[p];
+            col[p] = -col[p];
+        }
+        splat_params_add(scratch, i, s->m, col);   /* x + (-x) = 0 exactly */
+    }
+    free(col);
+}
+
 /* Gradient of L = sum_p dL_drgb[p] . rgb[p] over the listed pixels.
- * grads are ACCUMULATED (+=).  abs_sum (may be NULL) receives, per parameter,
- * the sum over pixels of |that pixel's contribution to the gradient|. */
+ * grads are ACCUMULATED (+=).  abs_sum (may be NULL) receives, per parameter
+ * p, the error scale sum over pixels and screen-space adjoints j of
+ * |J_pj| |s_j(pixel)|, with J the Jacobian of the reverse chain from the ten
+ * screen-space adjoints of the splat to its parameters: a computation that
+ * sums the per-pixel screen-space adjoints in finite precision and then
+ * applies the chain has an error bounded by a multiple of it. */
 int ob_render_bwd(const ob_splats *s, const ob_camera *cam, double alpha_max, double t_eps,
                   int64_t npix, const int32_t *pix_xy, const double *dL_drgb,
                   ob_grads *grads, ob_grads *abs_sum)
@@ -488,6 +550,25 @@ int ob_render_bwd(const ob_splats *s, const ob_camera *cam, double alpha_max, do
     if (scene_build(s, cam, &sc)) return -1;
     int64_t cap = sc.n_order > 0 ? sc.n_order : 1;
     int64_t chunk = 256;
+    const int q = n_params(s->m);
+    double **jac = NULL;
+    ob_grads scratch;
+    memset(&scratch, 0, sizeof(scratch));
+    if (abs_sum) {
+        size_t n1 = (size_t)(s->n > 0 ? s->n : 1);
+        size_t m1 = (size_t)(s->m > 0 ? s->m : 1);
+        jac = (double **)calloc(n1, sizeof(double *));
+        scratch.means = (double *)calloc(3 * n1, sizeof(double));
+        scratch.scales = (double *)calloc(3 * n1, sizeof(double));
+        scratch.quats = (double *)calloc(4 * n1, sizeof(double));
+        scratch.opacities = (double *)calloc(n1, sizeof(double));
+        scratch.betas = (double *)calloc(n1, sizeof(double));
+        scratch.diffuse = (double *)calloc(3 * n1, sizeof(double));
+        scratch.lobe_angles = (double *)calloc(2 * n1 * m1, sizeof(double));
+        scratch.lobe_colors = (double *)calloc(3 * n1 * m1, sizeof(double));
+        scratch.lobe_betas = (double *)calloc(n1 * m1, sizeof(double));
+    }
+    double *absv = (double *)malloc(sizeof(double) * (size_t)q);
     ob_step *steps = (ob_step *)malloc(sizeof(ob_step) * (size_t)cap * (size_t)chunk);
     int64_t *nsteps = (int64_t *)malloc(sizeof(int64_t) * (size_t)chunk);
     double *Tfin = (double *)malloc(sizeof(double) * (size_t)chunk);
@@ -535,10 +616,32 @@ int ob_render_bwd(const ob_splats *s, const ob_camera *cam, double alpha_max, do
                     sa.mean2d[0] = -adj_r2 * 2.0 * (f->conic[0] * e->dx + f->conic[1] * e->dy);
                     sa.mean2d[1] = -adj_r2 * 2.0 * (f->conic[1] * e->dx + f->conic[2] * e->dy);
                 }
-                chain_one(s, e->id, cam, f, &sa, grads, abs_sum);
+                chain_one(s, e->id, cam, f, &sa, grads);
+                if (abs_sum) {
+                    if (!jac[e->id]) {
+                        jac[e->id] = (double *)malloc(sizeof(double) * (size_t)q * 10);
+                        splat_jacobian(s, e->id, cam, f, &scratch, jac[e->id]);
+                    }
+                    const double *J = jac[e->id];
+                    const double *sv = (const double *)&sa;
+                    for (int pp2 = 0; pp2 < q; ++pp2) {
+                        double acc = 0.0;
+                        for (int j = 0; j < 10; ++j) acc += fabs(J[pp2 * 10 + j]) * fabs(sv[j]);
+                        absv[pp2] = acc;
+                    }
+                    splat_params_add(abs_sum, e->id, s->m, absv);
+                }
             }
         }
     }
+    if (abs_sum) {
+        for (int64_t i = 0; i < s->n; ++i) free(jac[i]);
+        free(jac);
+        free(scratch.means); free(scratch.scales); free(scratch.quats); free(scratch.opacities);
+        free(scratch.betas); free(scratch.diffuse); free(scratch.lobe_angles); free(scratch.lobe_colors);
+        free(scratch.lobe_betas);
+    }
+    free(absv);
     free(steps); free(nsteps); free(Tfin);
     scene_free(&sc);
     return 0;

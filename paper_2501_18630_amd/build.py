@@ -25,6 +25,7 @@ SOURCES = ["abi.hip", "preprocess.hip", "sort.hip", "raster.hip", "project_bwd.h
 # its rounding sequence is the written one.
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-function"]
 PER_FILE = {"preprocess.hip": ["-ffp-contract=off"], "project_bwd.hip": ["-ffp-contract=off"]}
 

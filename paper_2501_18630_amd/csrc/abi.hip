@@ -169,38 +169,73 @@ dbs_status dbs_render_fwd(const void *projected, const void *bins, const dbs_cam
                                         (hipStream_t)stream));
 }
 
-dbs_status dbs_render_bwd(const dbs_splats *splats, const void *projected, const void *bins, const dbs_camera *cams,
-                          int32_t n_views, const dbs_raster_cfg *cfg, const float *final_T, const int32_t *last_index,
-                          const float *dL_dimage, dbs_splat_grads *grads, void *workspace, size_t workspace_bytes,
-                          void *stream)
+static dbs_status check_grads(const dbs_splats *splats, const dbs_splat_grads *grads)
 {
-    DBS_TRY(check_splats(splats));
-    DBS_TRY(check_cams(cams, n_views));
-    DBS_TRY(check_cfg(cfg));
-    DBS_TRY(check_sizes(splats->n, n_views));
-    if (!projected || !bins || !final_T || !last_index || !dL_dimage || !grads || !workspace)
-        return DBS_ERR_INVALID_ARGUMENT;
+    if (!grads) return DBS_ERR_INVALID_ARGUMENT;
     if (splats->n > 0) {
         if (!grads->means || !grads->scales || !grads->quats || !grads->opacities || !grads->betas || !grads->diffuse)
             return DBS_ERR_INVALID_ARGUMENT;
         if (splats->m > 0 && (!grads->lobe_angles || !grads->lobe_colors || !grads->lobe_betas))
             return DBS_ERR_INVALID_ARGUMENT;
     }
-    const int64_t n = splats->n;
+    return DBS_OK;
+}
+
+dbs_status dbs_raster_bwd(const void *projected, const void *bins, const dbs_camera *cams, int32_t n_views,
+                          const dbs_raster_cfg *cfg, int64_t n, const float *final_T, const int32_t *last_index,
+                          const float *dL_dimage, void *stream)
+{
+    DBS_TRY(check_cams(cams, n_views));
+    DBS_TRY(check_cfg(cfg));
+    DBS_TRY(check_sizes(n, n_views));
+    if (!projected || !bins || !final_T || !last_index || !dL_dimage) return DBS_ERR_INVALID_ARGUMENT;
     const int64_t n_tiles = total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h);
-    const WorkLayout L = work_layout(n, n_views, 0, n_tiles);
-    if (workspace_bytes < L.bwd_total) return DBS_ERR_CAPACITY;
-    hipStream_t s = (hipStream_t)stream;
     ProjPtrs P = proj_ptrs((void *)projected, n, n_views);
     BinsPtrs B = bins_ptrs((void *)bins, n_tiles);
-    float *sgrad = (float *)((char *)workspace + L.sgrad);
-    DBS_TRY(hip_status(launch_zero_sgrad(P, n * n_views, sgrad, s)));
-    DBS_TRY(hip_status(launch_raster_bwd(P, B, n, n_views, n_tiles, *cfg, final_T, last_index, dL_dimage, sgrad, s)));
+    return hip_status(launch_raster_bwd(P, B, n, n_views, n_tiles, *cfg, final_T, last_index, dL_dimage,
+                                        (float *)P.sgrad, (hipStream_t)stream));
+}
+
+dbs_status dbs_project_bwd(const dbs_splats *splats, const void *projected, const dbs_camera *cams, int32_t n_views,
+                           const dbs_raster_cfg *cfg, dbs_splat_grads *grads, void *stream)
+{
+    DBS_TRY(check_splats(splats));
+    DBS_TRY(check_cams(cams, n_views));
+    DBS_TRY(check_cfg(cfg));
+    DBS_TRY(check_sizes(splats->n, n_views));
+    if (!projected) return DBS_ERR_INVALID_ARGUMENT;
+    DBS_TRY(check_grads(splats, grads));
+    ProjPtrs P = proj_ptrs((void *)projected, splats->n, n_views);
     GradPtrs g;
     g.means = grads->means; g.scales = grads->scales; g.quats = grads->quats; g.opacities = grads->opacities;
     g.betas = grads->betas; g.diffuse = grads->diffuse; g.lobe_angles = grads->lobe_angles;
     g.lobe_colors = grads->lobe_colors; g.lobe_betas = grads->lobe_betas;
-    return hip_status(launch_project_bwd(splat_ptrs(splats), P, n_views, sgrad, g, s));
+    return hip_status(launch_project_bwd(splat_ptrs(splats), P, n_views, g, (hipStream_t)stream));
+}
+
+dbs_status dbs_render_bwd(const dbs_splats *splats, const void *projected, const void *bins, const dbs_camera *cams,
+                          int32_t n_views, const dbs_raster_cfg *cfg, const float *final_T, const int32_t *last_index,
+                          const float *dL_dimage, dbs_splat_grads *grads, void *stream)
+{
+    DBS_TRY(check_splats(splats));
+    DBS_TRY(check_grads(splats, grads));
+    DBS_TRY(dbs_raster_bwd(projected, bins, cams, n_views, cfg, splats->n, final_T, last_index, dL_dimage, stream));
+    return dbs_project_bwd(splats, projected, cams, n_views, cfg, grads, stream);
+}
+
+dbs_status dbs_render_stats(const void *projected, const void *bins, const dbs_camera *cams, int32_t n_views,
+                            const dbs_raster_cfg *cfg, int64_t n, const float *final_T, const int32_t *last_index,
+                            int64_t *out, void *stream)
+{
+    DBS_TRY(check_cams(cams, n_views));
+    DBS_TRY(check_cfg(cfg));
+    DBS_TRY(check_sizes(n, n_views));
+    if (!projected || !bins || !final_T || !last_index || !out) return DBS_ERR_INVALID_ARGUMENT;
+    const int64_t n_tiles = total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h);
+    ProjPtrs P = proj_ptrs((void *)projected, n, n_views);
+    BinsPtrs B = bins_ptrs((void *)bins, n_tiles);
+    return hip_status(launch_raster_stats(P, B, n_views, n_tiles, *cfg, final_T, last_index, out,
+                                          (hipStream_t)stream));
 }
 
 dbs_status dbs_l1_loss(const float *image, const float *target, int64_t count, float scale, float *dL_dimage,

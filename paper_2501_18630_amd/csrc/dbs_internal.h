@@ -50,7 +50,7 @@ static_assert(sizeof(BinsHeader) == 128, "BinsHeader layout");
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 struct ProjLayout {
-    size_t header, views, centre, conic, color, bbox, depth, ntiles, total;
+    size_t header, views, centre, conic, color, bbox, depth, ntiles, sgrad, total;
 };
 inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     ProjLayout L;
@@ -63,6 +63,7 @@ inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     L.bbox = o;   o = align_up(o + 8 * R);
     L.depth = o;  o = align_up(o + 4 * R);
     L.ntiles = o; o = align_up(o + 4 * R);
+    L.sgrad = o;  o = align_up(o + 64 * R);   // screen-space gradient, one 64-byte line per record
     L.total = o;
     return L;
 }
@@ -97,8 +98,6 @@ struct WorkLayout {
     // bin/sort phase
     size_t keys_a, vals_a, keys_b, vals_b, pair_off, pkeys_a, pkeys_b, pvals_b, hist, partials,
         tkeys_a, tvals_a, tkeys_b, sort_total;
-    // backward phase
-    size_t sgrad, bwd_total;
     size_t total;
     int64_t hist_blocks;  // max sort blocks of any sort
 };
@@ -125,10 +124,7 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     L.tvals_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
     L.tkeys_b = o;  o = align_up(o + 4 * (size_t)n_tiles);
     L.sort_total = o;
-    size_t b = 0;
-    L.sgrad = b;    b = align_up(b + 48 * R);
-    L.bwd_total = b;
-    L.total = L.sort_total > L.bwd_total ? L.sort_total : L.bwd_total;
+    L.total = L.sort_total;
     return L;
 }
 
@@ -151,6 +147,7 @@ struct ProjPtrs {
     float4 *centre, *conic, *color;
     short4 *bbox;
     uint32_t *depth, *ntiles;
+    float4 *sgrad;  // [R][4]: dmu'(2), dA(3), do, db, dcolour(3), 6 unused
 };
 inline ProjPtrs proj_ptrs(void *base, int64_t n, int32_t n_views) {
     ProjLayout L = proj_layout(n, n_views);
@@ -164,6 +161,7 @@ inline ProjPtrs proj_ptrs(void *base, int64_t n, int32_t n_views) {
     p.bbox = (short4 *)(b + L.bbox);
     p.depth = (uint32_t *)(b + L.depth);
     p.ntiles = (uint32_t *)(b + L.ntiles);
+    p.sgrad = (float4 *)(b + L.sgrad);
     return p;
 }
 
@@ -206,10 +204,12 @@ hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
                              const dbs_raster_cfg &cfg, const float *final_T,
                              const int32_t *last_index, const float *dL_dimage, float *sgrad,
                              hipStream_t s);
+hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t n_tiles,
+                               const dbs_raster_cfg &cfg, const float *final_T, const int32_t *last_index,
+                               int64_t *out, hipStream_t s);
 // project_bwd.hip (also the L1 loss)
-hipError_t launch_zero_sgrad(ProjPtrs P, int64_t R, float *sgrad, hipStream_t s);
-hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, const float *sgrad,
-                              const GradPtrs &g, hipStream_t s);
+hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, const GradPtrs &g,
+                              hipStream_t s);
 hipError_t launch_l1_loss(const float *image, const float *target, int64_t count, float scale,
                           float *grad, float *loss, hipStream_t s);
 

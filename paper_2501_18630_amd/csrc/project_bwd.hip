@@ -1,10 +1,11 @@
 // Reverse pass of the projection and Spherical Beta colour.
 //
 // Input: per-record screen-space gradients accumulated by the raster reverse
-// pass, [R][12] floats: dL/dmu' (2), dL/dA for the symmetric conic
-// (A00, A01, A11 as full-matrix entries), dL/do, dL/db, dL/dcolour (3).
-// Output: dL/dparameter for every parameter of Sec. 3.2 Eq. (4) and
-// Sec. 3.3 Eq. (8), ADDED to the caller's buffers.
+// pass, one 64-byte line per record: dL/dmu' (2), dL/dA for the symmetric
+// conic (A00, A01, A11 as full-matrix entries), dL/do, dL/db, dL/dcolour (3).
+// Each line is cleared after it is read, so the accumulator is zero again
+// for the next reverse pass.  Output: dL/dparameter for every parameter of
+// Sec. 3.2 Eq. (4) and Sec. 3.3 Eq. (8), ADDED to the caller's buffers.
 //
 // Chain (Sec. 3.2):  A = Sigma'^{-1}  ->  dSigma' = -A G A;
 //   Sigma' = M Sigma M^T, M = J W  ->  dSigma = M^T dSigma' M, dM = 2 dSigma' M Sigma;
@@ -17,26 +18,15 @@
 // One thread per splat loops over the views: the per-splat gradient is summed
 // in registers (no atomics), Sigma's adjoint is summed over views before the
 // single chain to (q, s), and parameters are read and gradients written once.
-// The chain runs in FP64.
+// The geometric chain runs in FP64; the Spherical Beta lobes in FP32.
 #include "dbs_internal.h"
 
 namespace dbs {
 
 namespace {
 
-__global__ __launch_bounds__(256) void zero_sgrad_kernel(const uint32_t *ntiles, int64_t R, float4 *sgrad)
-{
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R || ntiles[r] == 0) return;
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    sgrad[3 * r] = z;
-    sgrad[3 * r + 1] = z;
-    sgrad[3 * r + 2] = z;
-}
-
 template <int M>
-__global__ __launch_bounds__(256) void project_bwd_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
-                                                          const float4 *__restrict__ sgrad, GradPtrs g)
+__global__ __launch_bounds__(256) void project_bwd_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views, GradPtrs g)
 {
     const int64_t n = sp.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -60,39 +50,43 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(SplatPtrs sp, ProjPtrs
             Sig[b][a] = acc;
         }
 
-    double lr[MM][3], dth[MM][3], dph[MM][3], lcol[MM][3], lbeta[MM];
+    float lr[MM][3], dth[MM][3], dph[MM][3], lcol[MM][3], lbeta[MM];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int64_t l = i * M + m;
-        const double th = sp.lobe_angles[2 * l], ph = sp.lobe_angles[2 * l + 1];
-        double st, ct, sph, cph;
-        sincos(th, &st, &ct);
-        sincos(ph, &sph, &cph);
+        float st, ct, sph, cph;
+        sincosf(sp.lobe_angles[2 * l], &st, &ct);
+        sincosf(sp.lobe_angles[2 * l + 1], &sph, &cph);
         lr[m][0] = st * cph; lr[m][1] = st * sph; lr[m][2] = ct;
         dth[m][0] = ct * cph; dth[m][1] = ct * sph; dth[m][2] = -st;
-        dph[m][0] = -st * sph; dph[m][1] = st * cph; dph[m][2] = 0.0;
+        dph[m][0] = -st * sph; dph[m][1] = st * cph; dph[m][2] = 0.0f;
         for (int c = 0; c < 3; ++c) lcol[m][c] = sp.lobe_colors[3 * l + c];
-        lbeta[m] = 4.0 * exp((double)sp.lobe_betas[l]);
+        lbeta[m] = 4.0f * expf(sp.lobe_betas[l]);
     }
 
     double gmu[3] = {0, 0, 0}, go = 0, gb = 0, gc0[3] = {0, 0, 0};
     double dSig[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    double gth[MM], gph[MM], gcm[MM][3], gbm[MM];
+    float gth[MM], gph[MM], gcm[MM][3], gbm[MM];
 #pragma unroll
     for (int m = 0; m < MM; ++m) {
-        gth[m] = gph[m] = gbm[m] = 0.0;
-        gcm[m][0] = gcm[m][1] = gcm[m][2] = 0.0;
+        gth[m] = gph[m] = gbm[m] = 0.0f;
+        gcm[m][0] = gcm[m][1] = gcm[m][2] = 0.0f;
     }
     bool any = false;
 
     for (int32_t v = 0; v < n_views; ++v) {
         const int64_t rec = (int64_t)v * n + i;
         if (P.ntiles[rec] == 0) continue;
-        const float4 ga = sgrad[3 * rec], gbv = sgrad[3 * rec + 1], gcv = sgrad[3 * rec + 2];
+        float4 *line = P.sgrad + 4 * rec;
+        const float4 ga = line[0], gbv = line[1], gcv = line[2];
         // ga = (dmu'x, dmu'y, G00, G01), gbv = (G11, do, db, dr), gcv = (dg, db_col, -, -)
         if (ga.x == 0.f && ga.y == 0.f && ga.z == 0.f && ga.w == 0.f && gbv.x == 0.f && gbv.y == 0.f &&
             gbv.z == 0.f && gbv.w == 0.f && gcv.x == 0.f && gcv.y == 0.f)
             continue;
+        {
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            line[0] = z; line[1] = z; line[2] = z; line[3] = z;
+        }
         any = true;
         const ViewDesc &V = P.views[v];
         const double W[9] = {V.R[0], V.R[1], V.R[2], V.R[3], V.R[4], V.R[5], V.R[6], V.R[7], V.R[8]};
@@ -129,19 +123,22 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(SplatPtrs sp, ProjPtrs
         const double vl = sqrt(vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
         const double Vd[3] = {vv[0] / vl, vv[1] / vl, vv[2] / vl};
         double adjV[3] = {0, 0, 0};
+        const float Vf[3] = {(float)Vd[0], (float)Vd[1], (float)Vd[2]};
+        const float gcf[3] = {gbv.w, gcv.x, gcv.y};
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const double d = lr[m][0] * Vd[0] + lr[m][1] * Vd[1] + lr[m][2] * Vd[2];
-            if (d > 0.0) {
-                const double pw = pow(d, lbeta[m] - 1.0);
-                const double wgt = pw * d;
-                const double adj_w = gcol[0] * lcol[m][0] + gcol[1] * lcol[m][1] + gcol[2] * lcol[m][2];
-                for (int c = 0; c < 3; ++c) gcm[m][c] += wgt * gcol[c];
-                gbm[m] += adj_w * wgt * log(d) * lbeta[m];
-                const double adj_d = adj_w * lbeta[m] * pw;
-                gth[m] += adj_d * (dth[m][0] * Vd[0] + dth[m][1] * Vd[1] + dth[m][2] * Vd[2]);
-                gph[m] += adj_d * (dph[m][0] * Vd[0] + dph[m][1] * Vd[1] + dph[m][2] * Vd[2]);
-                for (int k = 0; k < 3; ++k) adjV[k] += adj_d * lr[m][k];
+            const float d = lr[m][0] * Vf[0] + lr[m][1] * Vf[1] + lr[m][2] * Vf[2];
+            if (d > 0.0f) {
+                const float lgd = __builtin_amdgcn_logf(d);                 // log2 d
+                const float pw = __builtin_amdgcn_exp2f((lbeta[m] - 1.0f) * lgd);
+                const float wgt = pw * d;
+                const float adj_w = gcf[0] * lcol[m][0] + gcf[1] * lcol[m][1] + gcf[2] * lcol[m][2];
+                for (int c = 0; c < 3; ++c) gcm[m][c] += wgt * gcf[c];
+                gbm[m] += adj_w * wgt * (lgd * 0.69314718055994531f) * lbeta[m];
+                const float adj_d = adj_w * lbeta[m] * pw;
+                gth[m] += adj_d * (dth[m][0] * Vf[0] + dth[m][1] * Vf[1] + dth[m][2] * Vf[2]);
+                gph[m] += adj_d * (dph[m][0] * Vf[0] + dph[m][1] * Vf[1] + dph[m][2] * Vf[2]);
+                for (int k = 0; k < 3; ++k) adjV[k] += (double)(adj_d * lr[m][k]);
             }
         }
         const double vd = adjV[0] * Vd[0] + adjV[1] * Vd[1] + adjV[2] * Vd[2];
@@ -214,10 +211,10 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(SplatPtrs sp, ProjPtrs
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int64_t l = i * M + m;
-        g.lobe_angles[2 * l] += (float)gth[m];
-        g.lobe_angles[2 * l + 1] += (float)gph[m];
-        for (int c = 0; c < 3; ++c) g.lobe_colors[3 * l + c] += (float)gcm[m][c];
-        g.lobe_betas[l] += (float)gbm[m];
+        g.lobe_angles[2 * l] += gth[m];
+        g.lobe_angles[2 * l + 1] += gph[m];
+        for (int c = 0; c < 3; ++c) g.lobe_colors[3 * l + c] += gcm[m][c];
+        g.lobe_betas[l] += gbm[m];
     }
 }
 
@@ -225,6 +222,7 @@ __global__ __launch_bounds__(256) void l1_loss_kernel(const float *__restrict__ 
                                                       int64_t count, float scale, float *__restrict__ grad,
                                                       float *loss)
 {
+    __shared__ float s_part[256 / kWave];
     float acc = 0.0f;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
         const float d = img[k] - tgt[k];
@@ -233,7 +231,13 @@ __global__ __launch_bounds__(256) void l1_loss_kernel(const float *__restrict__ 
     }
     if (loss) {
         for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-        if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(loss, acc * scale);
+        if ((threadIdx.x & (kWave - 1)) == 0) s_part[threadIdx.x / kWave] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.0f;
+            for (int w = 0; w < 256 / kWave; ++w) t += s_part[w];
+            atomicAdd(loss, t * scale);
+        }
     }
 }
 
@@ -241,21 +245,12 @@ __global__ void zero_f32_kernel(float *p) { *p = 0.0f; }
 
 }  // namespace
 
-hipError_t launch_zero_sgrad(ProjPtrs P, int64_t R, float *sgrad, hipStream_t s)
-{
-    if (R > 0)
-        zero_sgrad_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(P.ntiles, R, (float4 *)sgrad);
-    return hipGetLastError();
-}
-
-hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, const float *sgrad,
-                              const GradPtrs &g, hipStream_t s)
+hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, const GradPtrs &g, hipStream_t s)
 {
     if (sp.n <= 0) return hipSuccess;
     dim3 grid((unsigned)ceil_div(sp.n, 256));
-    const float4 *sg = (const float4 *)sgrad;
     switch (sp.m) {
-#define DBS_PB(MM) case MM: project_bwd_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, sg, g); break;
+#define DBS_PB(MM) case MM: project_bwd_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, g); break;
         DBS_PB(0) DBS_PB(1) DBS_PB(2) DBS_PB(3) DBS_PB(4) DBS_PB(5) DBS_PB(6) DBS_PB(7) DBS_PB(8)
 #undef DBS_PB
         default: return hipErrorInvalidValue;
@@ -269,7 +264,7 @@ hipError_t launch_l1_loss(const float *image, const float *target, int64_t count
     if (loss) zero_f32_kernel<<<1, 1, 0, s>>>(loss);
     if (count > 0) {
         int64_t blocks = ceil_div(count, 256);
-        if (blocks > 8192) blocks = 8192;
+        if (blocks > 2048) blocks = 2048;
         l1_loss_kernel<<<(unsigned)blocks, 256, 0, s>>>(image, target, count, scale, grad, loss);
     }
     return hipGetLastError();

@@ -17,14 +17,19 @@
 //   dL/do = dL/dalpha B,  dL/db = dL/dalpha o B ln(1 - r^2) beta,
 //   dL/dr^2 = -dL/dalpha o beta B / (1 - r^2)  (all zero when alpha is clamped),
 //   dL/dmu' = -2 dL/dr^2 A d,   dL/dA = dL/dr^2 d d^T.
-// The ten per-(pixel, splat) values are summed over each wavefront, then over
-// the workgroup in LDS, then added once per (tile, splat) to the per-record
+// The ten per-(pixel, splat) values are summed over each wavefront with a
+// permlane/DPP butterfly (wave_reduce.h), then over the workgroup with LDS
+// float atomics, then added once per (tile, splat) to the per-record
 // screen-space gradient with a global float atomic.
+//
+// Each wavefront owns an 8x8 pixel block and walks only the splats whose
+// support can reach it (see `stage`).
 //
 // Work items are (view, tile) pairs.  A persistent grid drains a device
 // queue ordered heaviest tile first; the last workgroup to finish resets the
 // queue so that the next launch (or graph replay) starts from zero.
 #include "dbs_internal.h"
+#include "wave_reduce.h"
 
 namespace dbs {
 
@@ -43,7 +48,7 @@ struct RasterArgs {
     float *final_T;
     int32_t *last_index;
     const float *dL_dimage;
-    float *sgrad;     // [R][12]
+    float *sgrad;     // [R][16] screen-space gradient per record
     float t_eps, alpha_max;
     int32_t persistent;
 };
@@ -118,18 +123,95 @@ __device__ __forceinline__ void finish_persistent(const RasterArgs &a, uint32_t 
     }
 }
 
+// ---------------------------------------------------------------- staging
+//
+// Pixels are assigned so that each wavefront covers one 8x8 block of the tile
+// (block w at ((w % (TW/8)) * 8, (w / (TW/8)) * 8)).  When a batch of splats is
+// staged in LDS, the staging thread computes, for every block, the minimum
+// of r^2 over the block's pixel-centre rectangle; a block whose minimum is
+// at least 1 + 1e-4 cannot have a pixel with r^2 < 1 under FP32 rounding of
+// the per-pixel evaluation, so the splat is left out of that wave's list.
+// The lists change which (pixel, splat) pairs are evaluated, never a result.
+
+template <int TW, int TH>
+struct Geo {
+    static constexpr int NT = TW * TH;
+    static constexpr int NW = NT / kWave;  // waves = 8x8 blocks
+    static constexpr int BX = TW / 8;
+    static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 blocks");
+};
+
+// min over p in [x0,x1] x [y0,y1] of (p - c)^T A (p - c), A positive definite
+__device__ __forceinline__ float rect_min_r2(float cx, float cy, float a00, float a01, float a11, float x0,
+                                             float x1, float y0, float y1)
+{
+    const float dx0 = x0 - cx, dx1 = x1 - cx, dy0 = y0 - cy, dy1 = y1 - cy;
+    if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return 0.0f;
+    const float r00 = __builtin_amdgcn_rcpf(a00), r11 = __builtin_amdgcn_rcpf(a11);
+    float best = 3.0e38f;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float dx = e ? dx1 : dx0;
+        const float dy = fminf(fmaxf(-a01 * dx * r11, dy0), dy1);
+        best = fminf(best, a00 * dx * dx + 2.0f * a01 * dx * dy + a11 * dy * dy);
+        const float ey = e ? dy1 : dy0;
+        const float ex = fminf(fmaxf(-a01 * ey * r00, dx0), dx1);
+        best = fminf(best, a00 * ex * ex + 2.0f * a01 * ex * ey + a11 * ey * ey);
+    }
+    return best;
+}
+
+// Stage records [lo, lo + nb) of the pair list into LDS slot k = j - lo.
+template <int TW, int TH>
+__device__ __forceinline__ void stage(const RasterArgs &a, uint32_t lo, int nb, float fox, float foy, float4 *s_p,
+                                      float4 *s_q, float4 *s_c, int tid)
+{
+    using G = Geo<TW, TH>;
+    for (int k = tid; k < nb; k += G::NT) {
+        const uint32_t rec = a.pair_rec[lo + (uint32_t)k];
+        const float4 c = a.centre[rec], q = a.conic[rec], col = a.color[rec];
+        const float cx = __fadd_rn(__fsub_rn(c.x, fox), c.z), cy = __fadd_rn(__fsub_rn(c.y, foy), c.w);
+        uint32_t mask = 0;
+#pragma unroll
+        for (int w = 0; w < G::NW; ++w) {
+            const float bx = (float)((w % G::BX) * 8), by = (float)((w / G::BX) * 8);
+            const float m = rect_min_r2(cx, cy, q.x, q.y, q.z, bx + 0.5f, bx + 7.5f, by + 0.5f, by + 7.5f);
+            if (!(m >= 1.0001f)) mask |= 1u << w;
+        }
+        s_p[k] = make_float4(cx, cy, q.x, 2.0f * q.y);
+        s_q[k] = make_float4(q.z, q.w, col.w, col.x);
+        s_c[k] = make_float4(col.y, col.z, __uint_as_float(mask), __uint_as_float(rec));
+    }
+}
+
+// Wave `w` collects, in order, the slots whose mask has bit w.  Returns the count.
+__device__ __forceinline__ int build_list(const float4 *s_c, int nb, int w, uint8_t *list, int lane)
+{
+    int cnt = 0;
+    for (int base = 0; base < nb; base += kWave) {
+        const int k = base + lane;
+        const bool in = k < nb && ((__float_as_uint(s_c[k].z) >> w) & 1u);
+        const uint64_t bal = __ballot(in);
+        if (in) list[cnt + __popcll(bal & ((lane ? (~0ull >> (64 - lane)) : 0ull)))] = (uint8_t)k;
+        cnt += __popcll(bal);
+    }
+    return cnt;
+}
+
 // ---------------------------------------------------------------- forward
 
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
 {
-    constexpr int NT = TW * TH;
+    using G = Geo<TW, TH>;
+    static_assert(BATCH <= 256, "list entries are 8-bit");
     __shared__ float4 s_p[BATCH];  // local centre x, y, A00, 2 A01
     __shared__ float4 s_q[BATCH];  // A11, o, beta, r
-    __shared__ float2 s_c[BATCH];  // g, b
+    __shared__ float4 s_c[BATCH];  // g, b, wave mask, record
+    __shared__ uint8_t s_list[G::NW][BATCH];
     __shared__ Item s_item;
-    const int tid = threadIdx.x;
-    const int lx = tid % TW, ly = tid / TW;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const int lx = (w % G::BX) * 8 + (lane & 7), ly = (w / G::BX) * 8 + (lane >> 3);
     const float fpx = (float)lx + 0.5f, fpy = (float)ly + 0.5f;
 
     for (int iter = 0;; ++iter) {
@@ -145,21 +227,13 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
 
         for (uint32_t start = it.start; start < it.end; start += BATCH) {
             if (__syncthreads_count(!done) == 0) break;
-            for (int k = tid; k < BATCH; k += NT) {
-                const uint32_t j = start + (uint32_t)k;
-                if (j < it.end) {
-                    const uint32_t rec = a.pair_rec[j];
-                    const float4 c = a.centre[rec], q = a.conic[rec], col = a.color[rec];
-                    s_p[k] = make_float4(__fadd_rn(__fsub_rn(c.x, fox), c.z), __fadd_rn(__fsub_rn(c.y, foy), c.w),
-                                         q.x, 2.0f * q.y);
-                    s_q[k] = make_float4(q.z, q.w, col.w, col.x);
-                    s_c[k] = make_float2(col.y, col.z);
-                }
-            }
-            __syncthreads();
             const int nb = (int)min((uint32_t)BATCH, it.end - start);
+            stage<TW, TH>(a, start, nb, fox, foy, s_p, s_q, s_c, tid);
+            __syncthreads();
+            const int cnt = build_list(s_c, nb, w, s_list[w], lane);
             if (!done) {
-                for (int k = 0; k < nb; ++k) {
+                for (int t = 0; t < cnt; ++t) {
+                    const int k = s_list[w][t];
                     const float4 p = s_p[k];
                     const float dx = __fsub_rn(fpx, p.x), dy = __fsub_rn(fpy, p.y);
                     const float4 q = s_q[k];
@@ -168,11 +242,11 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                         float lg;
                         const float B = eval_kernel(r2, q.z, &lg);
                         const float alpha = fminf(a.alpha_max, __fmul_rn(q.y, B));
-                        const float w = alpha * T;
-                        const float2 cc = s_c[k];
-                        C0 = __fmaf_rn(q.w, w, C0);
-                        C1 = __fmaf_rn(cc.x, w, C1);
-                        C2 = __fmaf_rn(cc.y, w, C2);
+                        const float wgt = alpha * T;
+                        const float4 cc = s_c[k];
+                        C0 = __fmaf_rn(q.w, wgt, C0);
+                        C1 = __fmaf_rn(cc.x, wgt, C1);
+                        C2 = __fmaf_rn(cc.y, wgt, C2);
                         T = __fmul_rn(T, __fsub_rn(1.0f, alpha));
                         last = (int32_t)(start + (uint32_t)k);
                         if (T < a.t_eps) {
@@ -200,29 +274,34 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
 
 // ---------------------------------------------------------------- reverse
 
-__device__ __forceinline__ float wave_sum(float v)
+__device__ __forceinline__ int wave_max_i32(int v)
 {
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
     return v;
 }
 
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
 {
-    constexpr int NT = TW * TH;
+    using G = Geo<TW, TH>;
+    constexpr int NT = G::NT;
     constexpr int NG = 10;
     __shared__ float4 s_p[BATCH];
     __shared__ float4 s_q[BATCH];
-    __shared__ float2 s_c[BATCH];
-    __shared__ uint32_t s_rec[BATCH];
+    __shared__ float4 s_c[BATCH];
     __shared__ float s_g[BATCH][NG];
+    __shared__ uint8_t s_list[G::NW][BATCH];
     __shared__ Item s_item;
     __shared__ int32_t s_maxlast;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1);
-    const int lx = tid % TW, ly = tid / TW;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const int lx = (w % G::BX) * 8 + (lane & 7), ly = (w / G::BX) * 8 + (lane >> 3);
     const float fpx = (float)lx + 0.5f, fpy = (float)ly + 0.5f;
     const float kLn2 = 0.69314718055994531f;
+    // lanes holding the reduced sums (see wave_reduce.h)
+    const int row = lane >> 4;
+    const bool holder = (lane & 15) == 0;
+    const int f0 = reduce10_field0(row);
 
     for (int iter = 0;; ++iter) {
         if (!fetch_item<TW, TH>(a, &a.queue[2], &s_item, iter)) break;
@@ -242,34 +321,31 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
             g1 = gi[npx];
             g2 = gi[2 * npx];
         }
+        // last positions come from the forward over the same lists; keep them
+        // inside this tile's range so that no pair outside it is ever read
+        if (last >= (int32_t)it.end) last = (int32_t)it.end - 1;
         float S0 = T * V.bg[0], S1 = T * V.bg[1], S2 = T * V.bg[2];
         if (tid == 0) s_maxlast = -1;
         __syncthreads();
-        if (last >= 0) atomicMax(&s_maxlast, last);
+        const int32_t wave_last = wave_max_i32(last);
+        if (lane == 0 && wave_last >= 0) atomicMax(&s_maxlast, wave_last);
         __syncthreads();
-        // last positions come from the forward over the same lists; clamp them to
-        // this tile's range so that no pair outside it is ever read
-        const int64_t maxlast = s_maxlast < (int64_t)it.end ? (int64_t)s_maxlast : (int64_t)it.end - 1;
+        const int64_t maxlast = s_maxlast;
         const float fox = (float)it.ox, foy = (float)it.oy;
 
         if (maxlast >= (int64_t)it.start) {
             for (int64_t hi = maxlast + 1; hi > (int64_t)it.start; hi -= BATCH) {
                 const int64_t lo = hi - BATCH > (int64_t)it.start ? hi - BATCH : (int64_t)it.start;
                 const int nb = (int)(hi - lo);
-                for (int k = tid; k < nb; k += NT) {
-                    const uint32_t j = (uint32_t)(lo + k);
-                    const uint32_t rec = a.pair_rec[j];
-                    const float4 c = a.centre[rec], q = a.conic[rec], col = a.color[rec];
-                    s_p[k] = make_float4(__fadd_rn(__fsub_rn(c.x, fox), c.z), __fadd_rn(__fsub_rn(c.y, foy), c.w),
-                                         q.x, 2.0f * q.y);
-                    s_q[k] = make_float4(q.z, q.w, col.w, col.x);
-                    s_c[k] = make_float2(col.y, col.z);
-                    s_rec[k] = rec;
-#pragma unroll
-                    for (int f = 0; f < NG; ++f) s_g[k][f] = 0.0f;
-                }
+                stage<TW, TH>(a, (uint32_t)lo, nb, fox, foy, s_p, s_q, s_c, tid);
+                for (int idx = tid; idx < nb * NG; idx += NT) (&s_g[0][0])[idx] = 0.0f;
                 __syncthreads();
-                for (int k = nb - 1; k >= 0; --k) {
+                // this wave only needs its own splats up to its last contributor
+                const int64_t kmax64 = (int64_t)wave_last - lo;
+                const int nbw = kmax64 < (int64_t)(nb - 1) ? (int)kmax64 + 1 : nb;
+                const int cnt = nbw > 0 ? build_list(s_c, nbw, w, s_list[w], lane) : 0;
+                for (int t = cnt - 1; t >= 0; --t) {
+                    const int k = s_list[w][t];
                     const int32_t j = (int32_t)(lo + k);
                     float v[NG];
 #pragma unroll
@@ -287,24 +363,24 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                             const float araw = __fmul_rn(q.y, B);
                             const bool clamped = araw > a.alpha_max;
                             const float alpha = clamped ? a.alpha_max : araw;
-                            const float inv = 1.0f / (1.0f - alpha);
+                            const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
                             const float Ti = T * inv;
-                            const float w = alpha * Ti;
-                            const float2 cc = s_c[k];
-                            v[7] = g0 * w;
-                            v[8] = g1 * w;
-                            v[9] = g2 * w;
+                            const float wgt = alpha * Ti;
+                            const float4 cc = s_c[k];
+                            v[7] = g0 * wgt;
+                            v[8] = g1 * wgt;
+                            v[9] = g2 * wgt;
                             const float gc = g0 * q.w + g1 * cc.x + g2 * cc.y;
                             const float gS = g0 * S0 + g1 * S1 + g2 * S2;
                             const float dLda = Ti * gc - inv * gS;
-                            S0 = __fmaf_rn(q.w, w, S0);
-                            S1 = __fmaf_rn(cc.x, w, S1);
-                            S2 = __fmaf_rn(cc.y, w, S2);
+                            S0 = __fmaf_rn(q.w, wgt, S0);
+                            S1 = __fmaf_rn(cc.x, wgt, S1);
+                            S2 = __fmaf_rn(cc.y, wgt, S2);
                             T = Ti;
                             if (!clamped) {
                                 v[5] = dLda * B;
                                 v[6] = dLda * araw * (lg * kLn2) * q.z;
-                                const float gr2 = -dLda * q.z * araw / (1.0f - r2);
+                                const float gr2 = -dLda * q.z * araw * __builtin_amdgcn_rcpf(1.0f - r2);
                                 // d = p - mu': dr2/dmu' = -2 A d
                                 v[0] = -gr2 * (2.0f * p.z * dx + p.w * dy);
                                 v[1] = -gr2 * (p.w * dx + 2.0f * q.x * dy);
@@ -315,18 +391,21 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                         }
                     }
                     if (__ballot(contrib)) {
-#pragma unroll
-                        for (int f = 0; f < NG; ++f) {
-                            const float s = wave_sum(v[f]);
-                            if (lane == 0 && s != 0.0f) atomicAdd(&s_g[k][f], s);
+                        float o[3];
+                        wave_reduce10(v, o);
+                        if (holder) {
+                            atomicAdd(&s_g[k][f0], o[0]);
+                            atomicAdd(&s_g[k][f0 + 4], o[1]);
+                            if ((row & 1) == 0) atomicAdd(&s_g[k][8 + (row >> 1)], o[2]);
                         }
                     }
                 }
                 __syncthreads();
                 for (int idx = tid; idx < nb * NG; idx += NT) {
                     const int k = idx / NG, f = idx - k * NG;
-                    const float s = s_g[k][f];
-                    if (s != 0.0f) unsafeAtomicAdd(&a.sgrad[(int64_t)s_rec[k] * 12 + f], s);
+                    const float sg = s_g[k][f];
+                    if (sg != 0.0f)
+                        unsafeAtomicAdd(&a.sgrad[(int64_t)__float_as_uint(s_c[k].w) * 16 + f], sg);
                 }
                 __syncthreads();
             }
@@ -334,6 +413,49 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
         __syncthreads();
     }
     finish_persistent(a, &a.queue[2], &a.queue[3]);
+}
+
+// ---------------------------------------------------------------- work counts
+
+// One thread per pixel of a tile (tiles of TW x TH), plain loop over its list:
+// counts support tests and contributors with the same eval_r2 as above.
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void raster_stats_kernel(RasterArgs a, int64_t *out)
+{
+    const uint32_t g = blockIdx.x;
+    const int v = find_view(a.views, a.n_views, g);
+    const ViewDesc &V = a.views[v];
+    const uint32_t lt = g - (uint32_t)V.tile_offset;
+    const int ox = (int)(lt % (uint32_t)V.tiles_x) * TW, oy = (int)(lt / (uint32_t)V.tiles_x) * TH;
+    const int px = ox + (int)threadIdx.x % TW, py = oy + (int)threadIdx.x / TW;
+    const uint2 r = a.ranges[g];
+    uint64_t ev = 0, contrib = 0, ev_fwd = 0;
+    if (px < V.width && py < V.height) {
+        const int64_t pix = V.pixel_offset + (int64_t)py * V.width + px;
+        int32_t last = a.last_index[pix];
+        if (last >= (int32_t)r.y) last = (int32_t)r.y - 1;
+        const bool stopped = a.final_T[pix] < a.t_eps;
+        const float fpx = (float)(px - ox) + 0.5f, fpy = (float)(py - oy) + 0.5f;
+        for (int32_t j = (int32_t)r.x; j <= last; ++j) {
+            const uint32_t rec = a.pair_rec[j];
+            const float4 c = a.centre[rec], q = a.conic[rec];
+            const float cx = __fadd_rn(__fsub_rn(c.x, (float)ox), c.z), cy = __fadd_rn(__fsub_rn(c.y, (float)oy), c.w);
+            const float r2 = eval_r2(__fsub_rn(fpx, cx), __fsub_rn(fpy, cy), q.x, 2.0f * q.y, q.z);
+            contrib += r2 < 1.0f;
+        }
+        ev = last >= (int32_t)r.x ? (uint64_t)(last - (int32_t)r.x + 1) : 0;
+        ev_fwd = stopped ? ev : (uint64_t)(r.y - r.x);
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        ev += __shfl_xor(ev, off, kWave);
+        contrib += __shfl_xor(contrib, off, kWave);
+        ev_fwd += __shfl_xor(ev_fwd, off, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicAdd((unsigned long long *)&out[0], (unsigned long long)ev);
+        atomicAdd((unsigned long long *)&out[1], (unsigned long long)contrib);
+        atomicAdd((unsigned long long *)&out[2], (unsigned long long)ev_fwd);
+    }
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -458,5 +580,23 @@ hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
 }
 
 bool raster_supported(int tw, int th, int batch) { return find_entry(tw, th, batch) != nullptr; }
+
+hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t n_tiles, const dbs_raster_cfg &cfg,
+                               const float *final_T, const int32_t *last_index, int64_t *out, hipStream_t s)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    RasterArgs a = make_args(P, B, n_views, n_tiles, cfg);
+    a.final_T = (float *)final_T;
+    a.last_index = (int32_t *)last_index;
+    const int tw = cfg.tile_w, th = cfg.tile_h;
+    const dim3 grid((unsigned)n_tiles), block((unsigned)(tw * th));
+    if (tw == 16 && th == 16) raster_stats_kernel<16, 16><<<grid, block, 0, s>>>(a, out);
+    else if (tw == 16 && th == 8) raster_stats_kernel<16, 8><<<grid, block, 0, s>>>(a, out);
+    else if (tw == 8 && th == 8) raster_stats_kernel<8, 8><<<grid, block, 0, s>>>(a, out);
+    else if (tw == 32 && th == 8) raster_stats_kernel<32, 8><<<grid, block, 0, s>>>(a, out);
+    else if (tw == 32 && th == 16) raster_stats_kernel<32, 16><<<grid, block, 0, s>>>(a, out);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 }  // namespace dbs

@@ -96,7 +96,8 @@ class Rasterizer:
         pb = self.lib.dbs_projected_bytes(self.n, self.V)
         if pb == 0:
             raise ValueError("invalid splat or view count")
-        self.projected = torch.empty(pb, dtype=torch.uint8, device=self.device)
+        # zero-filled once: the reverse pass's accumulator lives in it
+        self.projected = torch.zeros(pb, dtype=torch.uint8, device=self.device)
         self.counts = torch.zeros(2, dtype=torch.int64, device=self.device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.capacity = -1
@@ -151,8 +152,30 @@ class Rasterizer:
         check("dbs_render_bwd", self.lib.dbs_render_bwd(
             C.byref(sp), C.c_void_p(self.projected.data_ptr()), C.c_void_p(self.bins.data_ptr()),
             self.cams_c, self.V, C.byref(self.cfg_c), C.c_void_p(final_T.data_ptr()),
-            C.c_void_p(last.data_ptr()), C.c_void_p(dL_dimage.data_ptr()), C.byref(gr),
-            C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(), _stream()))
+            C.c_void_p(last.data_ptr()), C.c_void_p(dL_dimage.data_ptr()), C.byref(gr), _stream()))
+
+    def raster_bwd(self, dL_dimage, final_T, last):
+        check("dbs_raster_bwd", self.lib.dbs_raster_bwd(
+            C.c_void_p(self.projected.data_ptr()), C.c_void_p(self.bins.data_ptr()), self.cams_c, self.V,
+            C.byref(self.cfg_c), self.n, C.c_void_p(final_T.data_ptr()), C.c_void_p(last.data_ptr()),
+            C.c_void_p(dL_dimage.data_ptr()), _stream()))
+
+    def project_bwd(self, params: dict, grads: dict):
+        sp = _splats_c(params, self.n, self.m)
+        gr = _grads_c(grads)
+        check("dbs_project_bwd", self.lib.dbs_project_bwd(
+            C.byref(sp), C.c_void_p(self.projected.data_ptr()), self.cams_c, self.V, C.byref(self.cfg_c),
+            C.byref(gr), _stream()))
+
+    def stats(self, final_T, last) -> dict:
+        """Evaluated / contributing (pixel, pair) counts of the last forward."""
+        out = torch.zeros(3, dtype=torch.int64, device=self.device)
+        check("dbs_render_stats", self.lib.dbs_render_stats(
+            C.c_void_p(self.projected.data_ptr()), C.c_void_p(self.bins.data_ptr()), self.cams_c, self.V,
+            C.byref(self.cfg_c), self.n, C.c_void_p(final_T.data_ptr()), C.c_void_p(last.data_ptr()),
+            C.c_void_p(out.data_ptr()), _stream()))
+        o = out.cpu().tolist()
+        return {"bwd_evaluated": o[0], "contributing": o[1], "fwd_evaluated": o[2]}
 
     # ---- eager helpers ----
     def forward(self, params: dict, outputs=None):

@@ -64,8 +64,9 @@ def assert_image_close(gpu_img_hw3, ref_rgb, ref_T, ref_T_prev, atol=1e-5):
 
 def assert_grads_close(g, g_ref, a_ref, rtol=1e-3, atol_abs=1e-5, names=PARAMS):
     """Per element |g - g_ref| <= rtol |g_ref| + atol_abs * A_ref, where A_ref is
-    the sum over pixels of |each pixel's contribution| (FP32 summation error
-    scales with it, not with |g_ref|); plus a per-tensor relative L2 check."""
+    the oracle's error scale sum_pixels sum_j |J_pj| |s_j| (the FP32 sums of
+    screen-space adjoints s_j carry an error proportional to sum |s_j|, which
+    the chain J maps to the parameters); plus a per-tensor relative L2 check."""
     for k in names:
         d = np.abs(g[k] - g_ref[k])
         tol = rtol * np.abs(g_ref[k]) + atol_abs * a_ref[k] + 1e-12

@@ -75,13 +75,21 @@ def test_gradient_with_early_termination_and_clamp(oracle):
     np.testing.assert_allclose(g["diffuse"][0], AMAX)
 
 
-def test_abs_sum_equals_abs_gradient_for_one_pixel(oracle):
+def test_error_scale_bounds_the_gradient(oracle):
+    """The error scale sum_pixels sum_j |J_pj| |s_j| is >= |gradient| for every
+    parameter, and equals it for one pixel where the chain from the screen
+    adjoints to the parameter has a single term (c0, c_m, o)."""
     cam = scenes.look_at_camera((1.0, 1.0, -4.0), 16, 16)
     s = fd_scene(7, n=3)
+    g, a = oracle.render_bwd(s, cam, AMAX, 0.0, np.random.default_rng(1).standard_normal((256, 3)),
+                             want_abs=True)
+    for k in PARAMS:
+        assert np.all(a[k] >= np.abs(g[k]) * (1 - 1e-12)), k
     pix = np.array([[8, 8]])
     g, a = oracle.render_bwd(s, cam, AMAX, 0.0, np.array([[0.3, -0.7, 1.1]]), pixels=pix, want_abs=True)
-    for k in PARAMS:
+    for k in ("diffuse", "lobe_colors", "opacities"):
         np.testing.assert_allclose(a[k], np.abs(g[k]), rtol=1e-12, atol=1e-300)
+    assert (g["diffuse"] != 0).any()
 
 
 # ---------------------------------------------------------------- binning
