@@ -22,7 +22,8 @@ struct alignas(16) ViewDesc {
     int32_t tile_offset;   // first global tile id of the view
     int32_t pad0;
     int64_t pixel_offset;  // first flat pixel of the view
-    int64_t pad1[2];
+    float campos[3];       // camera centre -R^T t (rounded from FP64)
+    int32_t pad1;
 };
 static_assert(sizeof(ViewDesc) == 128, "ViewDesc layout");
 
@@ -97,7 +98,7 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct WorkLayout {
     // bin/sort phase
     size_t keys_a, vals_a, keys_b, vals_b, pair_off, pkeys_a, pkeys_b, pvals_b, hist, partials,
-        tkeys_a, tvals_a, tkeys_b, sort_total;
+        tkeys_a, tvals_a, tkeys_b, sorted_box, sort_total;
     size_t total;
     int64_t hist_blocks;  // max sort blocks of any sort
 };
@@ -123,6 +124,7 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     L.tkeys_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
     L.tvals_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
     L.tkeys_b = o;  o = align_up(o + 4 * (size_t)n_tiles);
+    L.sorted_box = o; o = align_up(o + 8 * R);
     L.sort_total = o;
     L.total = L.sort_total;
     return L;

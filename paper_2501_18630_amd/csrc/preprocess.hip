@@ -214,6 +214,9 @@ hipError_t launch_upload_views(const dbs_camera *cams, int32_t n_views, int tile
             d.tiles_y = (c.height + tile_h - 1) / tile_h;
             d.tile_offset = tile_off;
             d.pixel_offset = pix_off;
+            for (int k = 0; k < 3; ++k)
+                d.campos[k] = (float)-((double)c.viewmat[k] * c.viewmat[3] + (double)c.viewmat[4 + k] * c.viewmat[7] +
+                                       (double)c.viewmat[8 + k] * c.viewmat[11]);
             tile_off += d.tiles_x * d.tiles_y;
             pix_off += (int64_t)c.width * c.height;
         }

@@ -17,6 +17,8 @@
 //   dL/do = dL/dalpha B,  dL/db = dL/dalpha o B ln(1 - r^2) beta,
 //   dL/dr^2 = -dL/dalpha o beta B / (1 - r^2)  (all zero when alpha is clamped),
 //   dL/dmu' = -2 dL/dr^2 A d,   dL/dA = dL/dr^2 d d^T.
+// The per-pixel terms are summed without their per-splat factors (o, beta,
+// A), which are applied once per (tile, splat) before the global atomics.
 // The ten per-(pixel, splat) values are summed over each wavefront with a
 // permlane/DPP butterfly (wave_reduce.h), then over the workgroup with LDS
 // float atomics, then added once per (tile, splat) to the per-record
@@ -347,60 +349,77 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 for (int t = cnt - 1; t >= 0; --t) {
                     const int k = s_list[w][t];
                     const int32_t j = (int32_t)(lo + k);
+                    const float4 p = s_p[k];
+                    const float4 q = s_q[k];
+                    const float dx = __fsub_rn(fpx, p.x), dy = __fsub_rn(fpy, p.y);
+                    const float r2 = eval_r2(dx, dy, p.z, p.w, q.x);
+                    const bool contrib = j <= last && r2 < 1.0f;
+                    if (!__ballot(contrib)) continue;
+                    // Branch-free from here: a lane that does not take part uses
+                    // r2 = 0 (finite logs) and alpha = 0 (T, S unchanged), and
+                    // its terms are multiplied by zero.
+                    float lg;
+                    const float r2c = contrib ? r2 : 0.0f;
+                    const float B = eval_kernel(r2c, q.z, &lg);
+                    const float araw = __fmul_rn(q.y, B);
+                    const bool clamped = araw > a.alpha_max;
+                    const float alpha = contrib ? (clamped ? a.alpha_max : araw) : 0.0f;
+                    const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                    const float Ti = T * inv;
+                    const float wgt = alpha * Ti;
+                    const float4 cc = s_c[k];
+                    const float gc = g0 * q.w + g1 * cc.x + g2 * cc.y;
+                    const float gS = g0 * S0 + g1 * S1 + g2 * S2;
+                    const float dLda = Ti * gc - inv * gS;
+                    S0 = __fmaf_rn(q.w, wgt, S0);
+                    S1 = __fmaf_rn(cc.x, wgt, S1);
+                    S2 = __fmaf_rn(cc.y, wgt, S2);
+                    T = contrib ? Ti : T;
+                    // per-splat factors (o, beta, A) are applied once after the sums
+                    const float t1 = (contrib && !clamped) ? dLda * B : 0.0f;
+                    const float gp = t1 * __builtin_amdgcn_rcpf(1.0f - r2c);
+                    const float u = gp * dx, wv = gp * dy;
                     float v[NG];
-#pragma unroll
-                    for (int f = 0; f < NG; ++f) v[f] = 0.0f;
-                    bool contrib = false;
-                    if (j <= last) {
-                        const float4 p = s_p[k];
-                        const float dx = __fsub_rn(fpx, p.x), dy = __fsub_rn(fpy, p.y);
-                        const float4 q = s_q[k];
-                        const float r2 = eval_r2(dx, dy, p.z, p.w, q.x);
-                        if (r2 < 1.0f) {
-                            contrib = true;
-                            float lg;
-                            const float B = eval_kernel(r2, q.z, &lg);
-                            const float araw = __fmul_rn(q.y, B);
-                            const bool clamped = araw > a.alpha_max;
-                            const float alpha = clamped ? a.alpha_max : araw;
-                            const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-                            const float Ti = T * inv;
-                            const float wgt = alpha * Ti;
-                            const float4 cc = s_c[k];
-                            v[7] = g0 * wgt;
-                            v[8] = g1 * wgt;
-                            v[9] = g2 * wgt;
-                            const float gc = g0 * q.w + g1 * cc.x + g2 * cc.y;
-                            const float gS = g0 * S0 + g1 * S1 + g2 * S2;
-                            const float dLda = Ti * gc - inv * gS;
-                            S0 = __fmaf_rn(q.w, wgt, S0);
-                            S1 = __fmaf_rn(cc.x, wgt, S1);
-                            S2 = __fmaf_rn(cc.y, wgt, S2);
-                            T = Ti;
-                            if (!clamped) {
-                                v[5] = dLda * B;
-                                v[6] = dLda * araw * (lg * kLn2) * q.z;
-                                const float gr2 = -dLda * q.z * araw * __builtin_amdgcn_rcpf(1.0f - r2);
-                                // d = p - mu': dr2/dmu' = -2 A d
-                                v[0] = -gr2 * (2.0f * p.z * dx + p.w * dy);
-                                v[1] = -gr2 * (p.w * dx + 2.0f * q.x * dy);
-                                v[2] = gr2 * dx * dx;
-                                v[3] = gr2 * dx * dy;
-                                v[4] = gr2 * dy * dy;
-                            }
-                        }
-                    }
-                    if (__ballot(contrib)) {
-                        float o[3];
-                        wave_reduce10(v, o);
-                        if (holder) {
-                            atomicAdd(&s_g[k][f0], o[0]);
-                            atomicAdd(&s_g[k][f0 + 4], o[1]);
-                            if ((row & 1) == 0) atomicAdd(&s_g[k][8 + (row >> 1)], o[2]);
-                        }
+                    v[0] = u;
+                    v[1] = wv;
+                    v[2] = u * dx;
+                    v[3] = u * dy;
+                    v[4] = wv * dy;
+                    v[5] = t1;
+                    v[6] = t1 * lg;
+                    v[7] = g0 * wgt;
+                    v[8] = g1 * wgt;
+                    v[9] = g2 * wgt;
+                    float o[3];
+                    wave_reduce10(v, o);
+                    if (holder) {
+                        atomicAdd(&s_g[k][f0], o[0]);
+                        atomicAdd(&s_g[k][f0 + 4], o[1]);
+                        if ((row & 1) == 0) atomicAdd(&s_g[k][8 + (row >> 1)], o[2]);
                     }
                 }
                 __syncthreads();
+                // per (tile, splat): apply the per-splat factors and add to the record.
+                // With gr2 = dL/dr^2 = -o beta g', d = p - mu':
+                //   dL/dmu' = -2 gr2 A d  = 2 o beta A (sum g' d)
+                //   dL/dA   = gr2 d d^T  = -o beta sum g' d d^T
+                //   dL/db   = o beta ln2 sum dLda B log2(1 - r^2)
+                for (int k = tid; k < nb; k += NT) {
+                    float *sg = s_g[k];
+                    const float4 p = s_p[k], q = s_q[k];
+                    const float ob = q.y * q.z;
+                    const float a00 = p.z, a01 = 0.5f * p.w, a11 = q.x;
+                    const float su = sg[0], sw = sg[1];
+                    sg[0] = 2.0f * ob * (a00 * su + a01 * sw);
+                    sg[1] = 2.0f * ob * (a01 * su + a11 * sw);
+                    sg[2] *= -ob;
+                    sg[3] *= -ob;
+                    sg[4] *= -ob;
+                    sg[6] *= ob * kLn2;
+                }
+                __syncthreads();
+                // consecutive lanes take consecutive values of a record: each wave-wide
+                // atomic touches a few 64-byte lines
                 for (int idx = tid; idx < nb * NG; idx += NT) {
                     const int k = idx / NG, f = idx - k * NG;
                     const float sg = s_g[k][f];

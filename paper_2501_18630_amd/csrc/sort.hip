@@ -82,11 +82,13 @@ __global__ __launch_bounds__(kSortThreads) void scan_reduce_kernel(Load ld, Coun
 {
     __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
     const int64_t n = cnt.get();
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 16;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
     uint32_t acc = 0;
 #pragma unroll 4
-    for (int k = 0; k < 16; ++k)
-        if (base + k < n) acc += ld(base + k);
+    for (int k = 0; k < 16; ++k) {
+        const int64_t e = base + (int64_t)k * kSortThreads;  // striped: coalesced
+        if (e < n) acc += ld(e);
+    }
     uint32_t total;
     block_exclusive_scan(acc, s_tmp, &total);
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
@@ -127,24 +129,45 @@ __global__ __launch_bounds__(1024) void scan_partials_kernel(uint32_t *partials,
     }
 }
 
+// Values are loaded striped (coalesced), transposed through LDS so that each
+// thread scans 16 consecutive elements, and the prefixes are handed back in
+// striped order to the store.
+__device__ __forceinline__ int scan_pad(int e) { return e + (e >> 4); }
+
 template <class Load, class Store>
 __global__ __launch_bounds__(kSortThreads) void scan_apply_kernel(Load ld, Store st, Count cnt,
                                                                   const uint32_t *partials)
 {
+    __shared__ uint32_t s_v[kScanTile + kScanTile / 16];
     __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
     const int64_t n = cnt.get();
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 16;
-    uint32_t v[16], acc = 0;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int t = threadIdx.x;
+    uint32_t v[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        v[k] = base + k < n ? ld(base + k) : 0u;
-        acc += v[k];
+        const int e = k * kSortThreads + t;
+        v[k] = base + e < n ? ld(base + e) : 0u;
+        s_v[scan_pad(e)] = v[k];
+    }
+    __syncthreads();
+    uint32_t loc[16], acc = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        loc[k] = s_v[scan_pad(t * 16 + k)];
+        acc += loc[k];
     }
     uint32_t pre = block_exclusive_scan(acc, s_tmp, nullptr) + partials[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        if (base + k < n) st(base + k, pre, v[k]);
-        pre += v[k];
+        s_v[scan_pad(t * 16 + k)] = pre;
+        pre += loc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int e = k * kSortThreads + t;
+        if (base + e < n) st(base + e, s_v[scan_pad(e)], v[k]);
     }
 }
 
@@ -191,21 +214,29 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
     s_cnt[threadIdx.x] = 0;
     __syncthreads();
     if (base < n) {
-        for (int k = 0; k < kSortItems; ++k) {
+        uint32_t d[kSortItems];
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before any ranking
             const int64_t e = base + (int64_t)k * kSortThreads + threadIdx.x;
-            const bool valid = e < n;
-            const uint32_t d = valid ? (keys[e] >> shift) & (kRadix - 1) : 0u;
-            const uint64_t peers = match_digit(d, valid);
-            if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
+            d[k] = e < n ? (keys[e] >> shift) & (kRadix - 1) : kRadix;
+        }
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const bool valid = d[k] < kRadix;
+            const uint64_t peers = match_digit(d[k], valid);
+            if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&s_cnt[d[k]], (uint32_t)__popcll(peers));
         }
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_cnt[threadIdx.x];
 }
 
+// If gather_src is set, also writes gather_out[o] = gather_src[value] at each
+// output position o (used to carry a per-value field through the last pass).
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
-    uint32_t *__restrict__ vals_out, Count cnt, int shift, const uint32_t *hist, int64_t nblocks)
+    uint32_t *__restrict__ vals_out, Count cnt, int shift, const uint32_t *hist, int64_t nblocks,
+    const uint2 *__restrict__ gather_src, uint2 *__restrict__ gather_out)
 {
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
@@ -230,11 +261,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking rounds
+        const int64_t e = base + (int64_t)k * kSortThreads + t;
+        key[k] = e < n ? keys_in[e] : 0u;
+        val[k] = e < n ? vals_in[e] : 0u;
+    }
+#pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t e = base + (int64_t)k * kSortThreads + t;
         const bool valid = e < n;
-        key[k] = valid ? keys_in[e] : 0u;
-        val[k] = valid ? vals_in[e] : 0u;
         const uint32_t d = (key[k] >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit(d, valid);
         const uint32_t in_wave = (uint32_t)__popcll(peers & lt);
@@ -275,15 +310,18 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
         const uint32_t kk = s_keys[j];
         const uint32_t d = (kk >> shift) & (kRadix - 1);
         const uint32_t o = s_goff[d] + (uint32_t)j - s_start[d];
+        const uint32_t vv = s_vals[j];
         keys_out[o] = kk;
-        vals_out[o] = s_vals[j];
+        vals_out[o] = vv;
+        if (gather_src) gather_out[o] = gather_src[vv];
     }
 }
 
 // Stable sort of (keys, vals) by key bits [bit_lo, bit_hi); ping-pongs
 // between the a and b buffers and reports where the result ended up.
 hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Count cnt, int bit_lo,
-                      int bit_hi, uint32_t *hist, uint32_t *partials, hipStream_t s, bool *result_in_b)
+                      int bit_hi, uint32_t *hist, uint32_t *partials, hipStream_t s, bool *result_in_b,
+                      const uint2 *gather_src = nullptr, uint2 *gather_out = nullptr)
 {
     const int64_t nblocks = ceil_div(cnt.host > 0 ? cnt.host : 1, kSortTile);
     bool in_b = false;
@@ -294,8 +332,10 @@ hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Co
         hipError_t e = device_scan(LoadArray{hist}, StoreArray{hist}, Count{nullptr, nblocks * kRadix},
                                    partials, s);
         if (e != hipSuccess) return e;
-        radix_downsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, cnt, shift,
-                                                                          hist, nblocks);
+        const bool final_pass = shift + kRadixBits >= bit_hi;
+        radix_downsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+            kin, vin, kout, vout, cnt, shift, hist, nblocks, final_pass ? gather_src : nullptr,
+            final_pass ? gather_out : nullptr);
         in_b = !in_b;
     }
     *result_in_b = in_b;
@@ -324,6 +364,17 @@ struct LoadVisible {
     const uint32_t *ntiles;
     __device__ uint32_t operator()(int64_t i) const { return ntiles[i] > 0 ? 1u : 0u; }
 };
+struct LoadTilesOfBox {
+    const uint2 *box;  // sorted pixel boxes (int16 x_lo, x_hi, y_lo, y_hi)
+    int tw, th;
+    __device__ uint32_t operator()(int64_t j) const
+    {
+        const uint2 u = box[j];
+        const int xl = (int)(int16_t)(u.x & 0xffffu), xh = (int)(int16_t)(u.x >> 16);
+        const int yl = (int)(int16_t)(u.y & 0xffffu), yh = (int)(int16_t)(u.y >> 16);
+        return (uint32_t)((xh / tw - xl / tw + 1) * (yh / th - yl / th + 1));
+    }
+};
 struct StoreCompact {
     const uint32_t *depth;
     uint32_t *keys, *vals;
@@ -335,30 +386,49 @@ struct StoreCompact {
         }
     }
 };
-struct LoadTilesOfSorted {
-    const uint32_t *ntiles, *sorted_rec;
-    __device__ uint32_t operator()(int64_t j) const { return ntiles[sorted_rec[j]]; }
-};
 
+// One block per 256 depth-ordered records: the block's pairs are generated
+// cooperatively, thread p writing pair p of the block (found by binary search
+// over the records' pair offsets), so that every store is contiguous.
 __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, const uint32_t *sorted_rec,
-                                                         const uint32_t *pair_off, const short4 *bbox,
+                                                         const uint32_t *pair_off, const short4 *sorted_box,
                                                          const ViewDesc *views, uint32_t n, int tw, int th,
                                                          uint32_t *pkeys, uint32_t *pvals)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (bh->overflow || j >= (int64_t)bh->n_vis) return;
-    const uint32_t rec = sorted_rec[j];
-    const uint32_t v = rec / n;
-    const short4 b = bbox[rec];
-    const ViewDesc &V = views[v];
-    const int tx0 = b.x / tw, tx1 = b.y / tw, ty0 = b.z / th, ty1 = b.w / th;
-    uint32_t o = pair_off[j];
-    for (int ty = ty0; ty <= ty1; ++ty) {
-        const uint32_t row = (uint32_t)V.tile_offset + (uint32_t)(ty * V.tiles_x);
-        for (int tx = tx0; tx <= tx1; ++tx, ++o) {
-            pkeys[o] = row + (uint32_t)tx;
-            pvals[o] = rec;
+    __shared__ uint32_t s_off[257];
+    __shared__ uint32_t s_rec[256], s_row0[256], s_tx[256];
+    __shared__ uint16_t s_w[256];
+    const int64_t j0 = (int64_t)blockIdx.x * 256;
+    const int64_t nvis = bh->n_vis;
+    if (bh->overflow || j0 >= nvis) return;  // uniform
+    const int cntb = nvis - j0 < 256 ? (int)(nvis - j0) : 256;
+    const int t = threadIdx.x;
+    if (t < cntb) {
+        const uint32_t rec = sorted_rec[j0 + t];
+        const short4 b = sorted_box[j0 + t];
+        const ViewDesc &V = views[rec / n];
+        const int tx0 = b.x / tw, tx1 = b.y / tw, ty0 = b.z / th, ty1 = b.w / th;
+        const uint32_t off = pair_off[j0 + t];
+        s_off[t] = off;
+        s_rec[t] = rec;
+        s_row0[t] = (uint32_t)V.tile_offset + (uint32_t)(ty0 * V.tiles_x + tx0);
+        s_tx[t] = (uint32_t)V.tiles_x;
+        s_w[t] = (uint16_t)(tx1 - tx0 + 1);
+        if (t == cntb - 1) s_off[cntb] = off + (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    }
+    __syncthreads();
+    const uint32_t base = s_off[0], total = s_off[cntb] - base;
+    for (uint32_t p = t; p < total; p += 256) {
+        const uint32_t gp = base + p;
+        int lo = 0, hi = cntb - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= gp) lo = mid; else hi = mid - 1;
         }
+        const uint32_t local = gp - s_off[lo], w = s_w[lo];
+        const uint32_t dy = local / w, dx = local - dy * w;
+        pkeys[gp] = s_row0[lo] + dy * s_tx[lo] + dx;
+        pvals[gp] = s_rec[lo];
     }
 }
 
@@ -412,6 +482,7 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     uint32_t *hist = (uint32_t *)(wb + L.hist), *partials = (uint32_t *)(wb + L.partials);
     uint32_t *tkeys_a = (uint32_t *)(wb + L.tkeys_a), *tvals_tmp = (uint32_t *)(wb + L.tvals_a);
     uint32_t *tkeys_b = (uint32_t *)(wb + L.tkeys_b);
+    uint2 *sorted_box = (uint2 *)(wb + L.sorted_box);
     const int64_t R = n * n_views;
     hipError_t e;
 
@@ -426,7 +497,9 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     const Count vis_cnt{&B.hdr->n_vis, R};
     bool depth_in_b = false;
     if (R > 0) {
-        e = radix_sort(keys_a, vals_a, keys_b, vals_b, vis_cnt, 0, 32, hist, partials, s, &depth_in_b);
+        // the last pass also writes each sorted record's pixel box contiguously
+        e = radix_sort(keys_a, vals_a, keys_b, vals_b, vis_cnt, 0, 32, hist, partials, s, &depth_in_b,
+                       (const uint2 *)P.bbox, sorted_box);
         if (e != hipSuccess) return e;
     }
     const uint32_t *sorted_rec = depth_in_b ? vals_b : vals_a;
@@ -437,11 +510,11 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     uint32_t *emit_vals = odd ? pvals_b : B.pair_rec;
     uint32_t *other_vals = odd ? B.pair_rec : pvals_b;
     if (R > 0 && cap > 0) {
-        e = device_scan(LoadTilesOfSorted{P.ntiles, sorted_rec}, StoreArray{pair_off}, vis_cnt, partials, s);
+        e = device_scan(LoadTilesOfBox{sorted_box, tile_w, tile_h}, StoreArray{pair_off}, vis_cnt, partials, s);
         if (e != hipSuccess) return e;
-        emit_pairs_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(B.hdr, sorted_rec, pair_off, P.bbox,
-                                                                     P.views, (uint32_t)n, tile_w, tile_h,
-                                                                     pkeys_a, emit_vals);
+        emit_pairs_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(B.hdr, sorted_rec, pair_off,
+                                                                     (const short4 *)sorted_box, P.views,
+                                                                     (uint32_t)n, tile_w, tile_h, pkeys_a, emit_vals);
         // 3. stable sort by global tile id
         bool pairs_in_b = false;
         const Count pair_cnt{&B.hdr->n_pairs, cap};
