@@ -56,11 +56,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=3)
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="auto", help="WxH, or auto (autotuned, outside the timed region)")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pixels", type=int, default=3072)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB buffer (reference for HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -141,8 +143,14 @@ def main():
     import torch
     from paper_2501_18630_amd import renderer, scenes
 
-    tw, th = (int(x) for x in args.tile.split("x"))
-    cfg = renderer.RasterConfig(tile_w=tw, tile_h=th, batch=args.batch)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4}))
+        return
+
     t0 = time.perf_counter()
     scene, cams = scenes.CONFIGS[args.config]()
     n, m = scene["means"].shape[0], scene["lobe_betas"].shape[1]
@@ -152,6 +160,16 @@ def main():
     targets = [scenes.target_image(c["height"], c["width"], seed=1 + v) for v, c in enumerate(cams)]
     target_flat = torch.as_tensor(np.concatenate([t.reshape(-1) for t in targets])).cuda()
     X = sum(c["width"] * c["height"] for c in cams)
+    if args.tile == "auto":
+        from paper_2501_18630_amd import autotune
+        t0 = time.perf_counter()
+        cfg = autotune.tune(cams, params, target_flat, log=log)
+        log(f"autotuned: {cfg.tile_w}x{cfg.tile_h} batch {cfg.batch} ({time.perf_counter() - t0:.1f} s)")
+        torch.cuda.empty_cache()
+    else:
+        tw, th = (int(x) for x in args.tile.split("x"))
+        cfg = renderer.RasterConfig(tile_w=tw, tile_h=th, batch=args.batch)
+    tw, th = cfg.tile_w, cfg.tile_h
 
     rast = renderer.Rasterizer(cams, n, m, cfg)
     step = renderer.TrainStep(rast, params, target_flat, headroom=1.1, use_graph=True)
@@ -211,7 +229,8 @@ def main():
         "dtype": "fp32",
         "data": "synthetic",
         "config": {"workload": f"config{args.config}: {len(cams)} views (sum {X} px), {n} splats, "
-                               f"{m} lobes, tile {tw}x{th}, batch {args.batch}, batched + hipGraph",
+                               f"{m} lobes, tile {tw}x{th}, batch {cfg.batch}"
+                               f"{' (autotuned)' if args.tile == 'auto' else ''}, batched + hipGraph",
                    "views": len(cams), "pixels": X, "splats": n, "lobes": m},
         "per_view_value": round(per_view, 3) if per_view else None,
         "batched_speedup": round(mpix / per_view, 3) if per_view else None,

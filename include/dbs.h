@@ -139,7 +139,8 @@ size_t dbs_workspace_bytes(int64_t n, int32_t n_views, int64_t pair_capacity,
 /* Projection of every (view, splat) record (Sec. 3.2: Sigma = R S S^T R^T,
  * Sigma' = J W Sigma W^T J^T, mu', conic Sigma'^{-1}, exact support box of
  * r^2 <= 1) and its Spherical Beta colour (Sec. 3.3, Eq. 8).  Geometry is
- * evaluated in FP64 and rounded once.  Writes `projected` and, if `counts`
+ * evaluated in FP64; the centre and conic are kept in FP64 for the raster
+ * passes, the pixel box and depth key are rounded once.  Writes `projected` and, if `counts`
  * is not NULL, counts[0] = visible records (at least one tile),
  * counts[1] = (tile, splat) pairs.  cams: [host] n_views cameras. */
 dbs_status dbs_preprocess(const dbs_splats *splats /*[host] struct of device pointers*/,
@@ -205,8 +206,11 @@ dbs_status dbs_project_bwd(const dbs_splats *splats /*[host] struct of device po
  *           tile's start to its last_index;
  * out[1] += those with r^2 < 1 (the pairs composited by Eq. 6);
  * out[2] += evaluations of the forward: list positions from the start to the
- *           pixel's last_index, or to the list end if it never stopped.
- * out: device int64[3], accumulated. */
+ *           pixel's last_index, or to the list end if it never stopped;
+ * out[3] += (wavefront, splat) list entries the reverse pass walks after its
+ *           per-8x8-block culling;
+ * out[4] += those entries in which at least one pixel has r^2 < 1.
+ * out: device int64[5], accumulated. */
 dbs_status dbs_render_stats(const void *projected, const void *bins, const dbs_camera *cams /*[host]*/,
                             int32_t n_views, const dbs_raster_cfg *cfg /*[host]*/, int64_t n,
                             const float *final_T, const int32_t *last_index, int64_t *out, void *stream);
@@ -223,16 +227,15 @@ dbs_status dbs_l1_loss(const float *image, const float *target, int64_t count, f
 
 /* Device pointers into `projected` for n splats and n_views views:
  * per record r = v n + i (view-major):
- *   centre [R] float4 (hi_x, hi_y, lo_x, lo_y): mu' = hi + lo in pixels
- *   conic  [R] float4 (A00, A01, A11, opacity)
- *   color  [R] float4 (r, g, b, 4 e^b)
+ *   record [R] 64-byte line: double cx, cy (mu' in pixels); double A00, A01,
+ *              A11 (conic); float o, 4 e^b; float r, g, b (colour); float pad
  *   bbox   [R] int16x4 (x_lo, x_hi, y_lo, y_hi) inclusive pixel box
  *   depth  [R] uint32 fp32 bits of the camera-space depth
  *   ntiles [R] uint32 number of tiles the box overlaps (0: culled/empty)
  *   counts     int64[2] (visible records, pairs)
- * Any output pointer may be NULL. */
-dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views,
-                                void **centre, void **conic, void **color, void **bbox,
+ * The record is written for records with ntiles > 0 only.  Any output
+ * pointer may be NULL. */
+dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views, void **record, void **bbox,
                                 void **depth, void **ntiles, void **counts);
 
 /* Device pointers into `bins`:

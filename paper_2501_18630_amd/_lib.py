@@ -72,7 +72,7 @@ def _declare(lib):
     lib.dbs_project_bwd.argtypes = [P, P, P, I32, P, P, P]
     lib.dbs_render_stats.argtypes = [P, P, P, I32, P, I64, P, P, P, P]
     lib.dbs_l1_loss.argtypes = [P, P, I64, C.c_float, P, P, P]
-    lib.dbs_projected_layout.argtypes = [P, I64, I32] + [C.POINTER(C.c_void_p)] * 7
+    lib.dbs_projected_layout.argtypes = [P, I64, I32] + [C.POINTER(C.c_void_p)] * 5
     lib.dbs_bins_layout.argtypes = [P, I64, P, I32, P] + [C.POINTER(C.c_void_p)] * 3 + [C.POINTER(C.c_int64)]
     for f in ("dbs_preprocess", "dbs_bin_sort", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
               "dbs_raster_bwd", "dbs_project_bwd", "dbs_render_stats",

@@ -1,0 +1,93 @@
+"""Autotuner for the raster launch shape: tile shape x LDS batch depth.
+
+For a given set of views and scene size it times the whole graph-captured
+training step (preprocess -> bin/sort -> forward -> L1 -> backward) for every
+built (tile_w, tile_h, batch) and keeps the fastest.  Results are cached in a
+JSON file keyed by the GPU architecture, the view resolutions and the splat
+and lobe counts, so a workload is tuned once per machine type.
+
+    cfg = autotune.tune(cams, params, target)      # RasterConfig
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import torch
+
+from . import renderer
+
+CANDIDATES = [(16, 16), (16, 8), (8, 8), (32, 8), (32, 16)]
+BATCHES = [64, 128, 256]
+CACHE = os.environ.get("DBS_AUTOTUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "dbs_autotune.json"))
+
+
+def workload_key(cams, n: int, m: int) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
+    res = ",".join(f"{c['width']}x{c['height']}" for c in cams)
+    return f"{arch}|{n}|{m}|{res}"
+
+
+def _load_cache(path: str) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(path: str, cache: dict):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_config(cams, params, target, cfg: renderer.RasterConfig, steps: int = 3, warmup: int = 1) -> float:
+    """Seconds per graph-replayed training step for one launch shape."""
+    n = params["means"].shape[0]
+    m = params["lobe_betas"].shape[1]
+    rast = renderer.Rasterizer(cams, n, m, cfg)
+    step = renderer.TrainStep(rast, params, target, headroom=1.1, use_graph=True)
+    for _ in range(warmup):
+        step.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    if step.overflowed():
+        dt = float("inf")
+    del step, rast
+    return dt
+
+
+def tune(cams, params, target, candidates=None, batches=None, cache_path: str | None = CACHE,
+         steps: int = 3, log=None) -> renderer.RasterConfig:
+    """Fastest RasterConfig for this workload (cached)."""
+    n = params["means"].shape[0]
+    m = params["lobe_betas"].shape[1]
+    key = workload_key(cams, n, m)
+    cache = _load_cache(cache_path) if cache_path else {}
+    if key in cache:
+        e = cache[key]
+        return renderer.RasterConfig(tile_w=e["tile_w"], tile_h=e["tile_h"], batch=e["batch"])
+    best, best_t, table = None, float("inf"), []
+    for tw, th in candidates or CANDIDATES:
+        for b in batches or BATCHES:
+            cfg = renderer.RasterConfig(tile_w=tw, tile_h=th, batch=b)
+            t = time_config(cams, params, target, cfg, steps=steps)
+            table.append({"tile_w": tw, "tile_h": th, "batch": b, "ms": round(t * 1e3, 4)})
+            if log:
+                log(f"autotune {tw}x{th} batch {b}: {t * 1e3:.3f} ms")
+            if t < best_t:
+                best, best_t = cfg, t
+    if cache_path:
+        cache[key] = {"tile_w": best.tile_w, "tile_h": best.tile_h, "batch": best.batch,
+                      "ms": round(best_t * 1e3, 4), "table": table}
+        _save_cache(cache_path, cache)
+    return best

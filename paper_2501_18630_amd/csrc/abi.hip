@@ -246,14 +246,12 @@ dbs_status dbs_l1_loss(const float *image, const float *target, int64_t count, f
     return hip_status(launch_l1_loss(image, target, count, scale, dL_dimage, loss, (hipStream_t)stream));
 }
 
-dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views, void **centre, void **conic,
-                                void **color, void **bbox, void **depth, void **ntiles, void **counts)
+dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views, void **record, void **bbox,
+                                void **depth, void **ntiles, void **counts)
 {
     if (!projected || n < 0 || n_views < 1 || n_views > DBS_MAX_VIEWS) return DBS_ERR_INVALID_ARGUMENT;
     ProjPtrs P = proj_ptrs(projected, n, n_views);
-    if (centre) *centre = P.centre;
-    if (conic) *conic = P.conic;
-    if (color) *color = P.color;
+    if (record) *record = P.rec;
     if (bbox) *bbox = P.bbox;
     if (depth) *depth = P.depth;
     if (ntiles) *ntiles = P.ntiles;

@@ -50,17 +50,26 @@ static_assert(sizeof(BinsHeader) == 128, "BinsHeader layout");
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+// One 64-byte, line-aligned raster record per (view, splat): everything a
+// raster pass gathers for a pair comes in one cache line.
+struct alignas(64) RasterRec {
+    double cx, cy;          // mu' in pixels (FP64)
+    double a00, a01, a11;   // conic Sigma'^{-1} (FP64)
+    float opacity, beta;    // o, 4 e^b
+    float r, g, b;          // Spherical Beta colour of this view
+    float pad;
+};
+static_assert(sizeof(RasterRec) == 64, "RasterRec layout");
+
 struct ProjLayout {
-    size_t header, views, centre, conic, color, bbox, depth, ntiles, sgrad, total;
+    size_t header, views, rec, bbox, depth, ntiles, sgrad, total;
 };
 inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     ProjLayout L;
     size_t R = (size_t)n * (size_t)n_views, o = 0;
     L.header = o; o = align_up(o + sizeof(ProjHeader));
     L.views = o;  o = align_up(o + sizeof(ViewDesc) * (size_t)n_views);
-    L.centre = o; o = align_up(o + 16 * R);
-    L.conic = o;  o = align_up(o + 16 * R);
-    L.color = o;  o = align_up(o + 16 * R);
+    L.rec = o;    o = align_up(o + 64 * R);
     L.bbox = o;   o = align_up(o + 8 * R);
     L.depth = o;  o = align_up(o + 4 * R);
     L.ntiles = o; o = align_up(o + 4 * R);
@@ -146,7 +155,7 @@ struct GradPtrs {
 struct ProjPtrs {
     ProjHeader *hdr;
     ViewDesc *views;
-    float4 *centre, *conic, *color;
+    RasterRec *rec;
     short4 *bbox;
     uint32_t *depth, *ntiles;
     float4 *sgrad;  // [R][4]: dmu'(2), dA(3), do, db, dcolour(3), 6 unused
@@ -157,9 +166,7 @@ inline ProjPtrs proj_ptrs(void *base, int64_t n, int32_t n_views) {
     ProjPtrs p;
     p.hdr = (ProjHeader *)(b + L.header);
     p.views = (ViewDesc *)(b + L.views);
-    p.centre = (float4 *)(b + L.centre);
-    p.conic = (float4 *)(b + L.conic);
-    p.color = (float4 *)(b + L.color);
+    p.rec = (RasterRec *)(b + L.rec);
     p.bbox = (short4 *)(b + L.bbox);
     p.depth = (uint32_t *)(b + L.depth);
     p.ntiles = (uint32_t *)(b + L.ntiles);

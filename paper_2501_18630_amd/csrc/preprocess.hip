@@ -13,9 +13,10 @@
 // HBM once per call however many views are rendered.  Geometry is computed in
 // FP64 (exact products of the FP32 inputs, then rounded once): the pixel box
 // and the depth key are integer decisions that must not depend on FP32
-// rounding, and the centre is kept as an FP32 hi/lo pair so that pixel
-// offsets can be formed without the absolute-coordinate rounding of a single
-// FP32 value (ulp(1400) ~ 1.2e-4 px).
+// rounding.  The record keeps the centre and the conic in FP64: the raster
+// passes evaluate r^2 in FP64, because the Beta kernel's slope at the
+// support edge, beta (1 - r^2)^(beta - 1), is unbounded for beta < 1 and an
+// FP32 r^2 would carry a large relative error in 1 - r^2 there.
 #include "dbs_internal.h"
 
 namespace dbs {
@@ -52,7 +53,7 @@ __device__ inline uint64_t wave_sum_u64(uint64_t v)
 
 template <int M>
 __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
-                                                         int32_t tw, int32_t th)
+                                                         int32_t lw, int32_t lh)
 {
     const int64_t n = sp.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,8 +114,9 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
             if (ok && tc[2] > (double)V.near_plane) {
                 const double tx = tc[0], ty = tc[1], tz = tc[2];
                 const double fx = V.fx, fy = V.fy;
-                const double J00 = fx / tz, J02 = -fx * tx / (tz * tz);
-                const double J11 = fy / tz, J12 = -fy * ty / (tz * tz);
+                const double iz = 1.0 / tz, iz2 = iz * iz;
+                const double J00 = fx * iz, J02 = -fx * tx * iz2;
+                const double J11 = fy * iz, J12 = -fy * ty * iz2;
                 // M = J W (2x3)
                 double Mm[2][3];
                 for (int b = 0; b < 3; ++b) {
@@ -131,8 +133,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
                 const double c11 = Tm[1][0] * Mm[1][0] + Tm[1][1] * Mm[1][1] + Tm[1][2] * Mm[1][2];
                 const double det = c00 * c11 - c01 * c01;
                 if (det > 0.0) {
-                    const double mx = fx * tx / tz + (double)V.cx;
-                    const double my = fy * ty / tz + (double)V.cy;
+                    const double mx = fx * tx * iz + (double)V.cx;
+                    const double my = fy * ty * iz + (double)V.cy;
                     const double ex = sqrt(c00), ey = sqrt(c11);
                     double xl = ceil(mx - ex - 0.5), xh = floor(mx + ex - 0.5);
                     double yl = ceil(my - ey - 0.5), yh = floor(my + ey - 0.5);
@@ -143,17 +145,23 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
                     if (xl <= xh && yl <= yh) {
                         const int ixl = (int)xl, ixh = (int)xh, iyl = (int)yl, iyh = (int)yh;
                         bb = make_short4((short)ixl, (short)ixh, (short)iyl, (short)iyh);
-                        ntiles = (uint32_t)((ixh / tw - ixl / tw + 1) * (iyh / th - iyl / th + 1));
-                        const float hx = (float)mx, hy = (float)my;
-                        P.centre[rec] = make_float4(hx, hy, (float)(mx - (double)hx), (float)(my - (double)hy));
-                        P.conic[rec] = make_float4((float)(c11 / det), (float)(-c01 / det), (float)(c00 / det), opac);
+                        ntiles = (uint32_t)(((ixh >> lw) - (ixl >> lw) + 1) * ((iyh >> lh) - (iyl >> lh) + 1));
+                        const double idet = 1.0 / det;
+                        RasterRec rr;
+                        rr.cx = mx;
+                        rr.cy = my;
+                        rr.a00 = c11 * idet;
+                        rr.a01 = -c01 * idet;
+                        rr.a11 = c00 * idet;
+                        rr.opacity = opac;
+                        rr.beta = beta;
                         // Spherical Beta colour; V = (mu - camera centre) / |.|
                         double cp[3];
                         for (int k = 0; k < 3; ++k)
                             cp[k] = -(W[k] * (double)V.t[0] + W[3 + k] * (double)V.t[1] + W[6 + k] * (double)V.t[2]);
-                        double vx = mu[0] - cp[0], vy = mu[1] - cp[1], vz = mu[2] - cp[2];
-                        double vl = sqrt(vx * vx + vy * vy + vz * vz);
-                        const float dx = (float)(vx / vl), dy = (float)(vy / vl), dz = (float)(vz / vl);
+                        const double vx = mu[0] - cp[0], vy = mu[1] - cp[1], vz = mu[2] - cp[2];
+                        const double ivl = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
+                        const float dx = (float)(vx * ivl), dy = (float)(vy * ivl), dz = (float)(vz * ivl);
                         float cr = c0r, cg = c0g, cb = c0b;
 #pragma unroll
                         for (int mm = 0; mm < M; ++mm) {
@@ -165,7 +173,11 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
                                 cb += wgt * lc[mm][2];
                             }
                         }
-                        P.color[rec] = make_float4(cr, cg, cb, beta);
+                        rr.r = cr;
+                        rr.g = cg;
+                        rr.b = cb;
+                        rr.pad = 0.0f;
+                        P.rec[rec] = rr;
                         vis += 1;
                         pairs += ntiles;
                     }
@@ -230,9 +242,14 @@ hipError_t launch_preprocess(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, i
                              int tile_h, int64_t *counts_out, hipStream_t s)
 {
     if (sp.n > 0) {
+        // tile sizes are powers of two: pixel -> tile is a shift
+        int lw = 0, lh = 0;
+        while ((1 << lw) < tile_w) ++lw;
+        while ((1 << lh) < tile_h) ++lh;
+        if ((1 << lw) != tile_w || (1 << lh) != tile_h) return hipErrorInvalidValue;
         dim3 grid((unsigned)ceil_div(sp.n, 256));
         switch (sp.m) {
-#define DBS_PRE(MM) case MM: preprocess_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, tile_w, tile_h); break;
+#define DBS_PRE(MM) case MM: preprocess_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, lw, lh); break;
             DBS_PRE(0) DBS_PRE(1) DBS_PRE(2) DBS_PRE(3) DBS_PRE(4)
             DBS_PRE(5) DBS_PRE(6) DBS_PRE(7) DBS_PRE(8)
 #undef DBS_PRE

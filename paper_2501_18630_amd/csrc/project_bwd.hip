@@ -173,8 +173,15 @@ __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp,
 }
 
 // Colour (Sec. 3.3, Eq. 8): dL/dcolour -> c0, lobes (theta, phi, c_m, b_m) and
-// mu through the view direction.  FP32 lobes.  Runs after the geometry
-// kernel and clears every line it reads.
+// mu through the view direction.  Runs after the geometry kernel and clears
+// every line it reads.
+//
+// The lobe factor d = R_m . V is evaluated in FP64 (directions from FP64
+// sin/cos, V normalised in FP64): near alignment 1 - d, dd/dtheta, dd/dphi and
+// the component of the lobe pull orthogonal to V are all O(angle) or smaller,
+// and FP32 directions carry ~1e-7 absolute error that swamps them (log d, and
+// with it dL/db_m, loses all relative accuracy as d -> 1).  ln d is taken from
+// whichever of d and d - 1 is exact, then the powers run in FP32.
 template <int M>
 __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
                                                                 GradPtrs g)
@@ -183,13 +190,14 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     constexpr int MM = M > 0 ? M : 1;
-    const float mu[3] = {sp.means[3 * i], sp.means[3 * i + 1], sp.means[3 * i + 2]};
-    float st[MM], ct[MM], sph[MM], cph[MM], lcol[MM][3], lbeta[MM];
+    const double mu[3] = {sp.means[3 * i], sp.means[3 * i + 1], sp.means[3 * i + 2]};
+    double st[MM], ct[MM], sph[MM], cph[MM];
+    float lcol[MM][3], lbeta[MM];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int64_t l = i * M + m;
-        sincosf(sp.lobe_angles[2 * l], &st[m], &ct[m]);
-        sincosf(sp.lobe_angles[2 * l + 1], &sph[m], &cph[m]);
+        sincos((double)sp.lobe_angles[2 * l], &st[m], &ct[m]);
+        sincos((double)sp.lobe_angles[2 * l + 1], &sph[m], &cph[m]);
         for (int c = 0; c < 3; ++c) lcol[m][c] = sp.lobe_colors[3 * l + c];
         lbeta[m] = 4.0f * expf(sp.lobe_betas[l]);
     }
@@ -217,32 +225,36 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
         for (int c = 0; c < 3; ++c) gc0[c] += gcf[c];
         if (M == 0) continue;
         const ViewDesc &V = P.views[v];
-        const float vv0 = mu[0] - V.campos[0], vv1 = mu[1] - V.campos[1], vv2 = mu[2] - V.campos[2];
-        const float ivl = __builtin_amdgcn_rsqf(vv0 * vv0 + vv1 * vv1 + vv2 * vv2);
-        const float Vf[3] = {vv0 * ivl, vv1 * ivl, vv2 * ivl};
-        float aV[3] = {0.f, 0.f, 0.f};
+        double vd3[3];
+        for (int k = 0; k < 3; ++k)
+            vd3[k] = mu[k] + ((double)V.R[k] * V.t[0] + (double)V.R[3 + k] * V.t[1] + (double)V.R[6 + k] * V.t[2]);
+        const double ivl = 1.0 / sqrt(vd3[0] * vd3[0] + vd3[1] * vd3[1] + vd3[2] * vd3[2]);
+        const double Vd[3] = {vd3[0] * ivl, vd3[1] * ivl, vd3[2] * ivl};
+        double aV[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const float lr0 = st[m] * cph[m], lr1 = st[m] * sph[m], lr2 = ct[m];
-            const float d = lr0 * Vf[0] + lr1 * Vf[1] + lr2 * Vf[2];
-            if (d > 0.0f) {
-                const float lgd = __builtin_amdgcn_logf(d);                 // log2 d
-                const float pw = __builtin_amdgcn_exp2f((lbeta[m] - 1.0f) * lgd);
-                const float wgt = pw * d;
+            const double lr0 = st[m] * cph[m], lr1 = st[m] * sph[m], lr2 = ct[m];
+            const double d = lr0 * Vd[0] + lr1 * Vd[1] + lr2 * Vd[2];
+            if (d > 0.0) {
+                const float lnd = d < 0.5 ? logf((float)d) : log1pf((float)(d - 1.0));
+                const float pw = expf((lbeta[m] - 1.0f) * lnd);             // d^(beta-1)
+                const float wgt = pw * (float)d;                             // d^beta
                 const float adj_w = gcf[0] * lcol[m][0] + gcf[1] * lcol[m][1] + gcf[2] * lcol[m][2];
                 for (int c = 0; c < 3; ++c) gcm[m][c] += wgt * gcf[c];
-                gbm[m] += adj_w * wgt * (lgd * 0.69314718055994531f) * lbeta[m];
+                gbm[m] += adj_w * wgt * lnd * lbeta[m];
                 const float adj_d = adj_w * lbeta[m] * pw;
                 // dR/dtheta = (ct cph, ct sph, -st), dR/dphi = (-st sph, st cph, 0)
-                gth[m] += adj_d * (ct[m] * cph[m] * Vf[0] + ct[m] * sph[m] * Vf[1] - st[m] * Vf[2]);
-                gph[m] += adj_d * (-lr1 * Vf[0] + lr0 * Vf[1]);
+                const double dth = ct[m] * (cph[m] * Vd[0] + sph[m] * Vd[1]) - st[m] * Vd[2];
+                const double dph = lr0 * Vd[1] - lr1 * Vd[0];
+                gth[m] += adj_d * (float)dth;
+                gph[m] += adj_d * (float)dph;
                 aV[0] += adj_d * lr0;
                 aV[1] += adj_d * lr1;
                 aV[2] += adj_d * lr2;
             }
         }
-        const float vd = aV[0] * Vf[0] + aV[1] * Vf[1] + aV[2] * Vf[2];
-        for (int k = 0; k < 3; ++k) gmu[k] += (aV[k] - Vf[k] * vd) * ivl;
+        const double vdot = aV[0] * Vd[0] + aV[1] * Vd[1] + aV[2] * Vd[2];
+        for (int k = 0; k < 3; ++k) gmu[k] += (float)((aV[k] - Vd[k] * vdot) * ivl);
     }
     if (!any) return;
     for (int k = 0; k < 3; ++k) {

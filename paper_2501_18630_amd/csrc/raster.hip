@@ -41,7 +41,7 @@ struct RasterArgs {
     const ViewDesc *views;
     int32_t n_views;
     uint32_t n_tiles;
-    const float4 *centre, *conic, *color;
+    const RasterRec *rec;
     const uint32_t *pair_rec;
     const uint2 *ranges;
     const uint32_t *order;
@@ -55,21 +55,25 @@ struct RasterArgs {
     int32_t persistent;
 };
 
-// r^2 = A00 dx^2 + 2 A01 dx dy + A11 dy^2 with a fixed rounding sequence, so
-// that the forward and reverse kernels take identical support decisions.
-__device__ __forceinline__ float eval_r2(float dx, float dy, float a00, float a01x2, float a11)
+// r^2 = A00 dx^2 + 2 A01 dx dy + A11 dy^2 in FP64 with a fixed rounding
+// sequence, so that the forward and reverse kernels take identical support
+// decisions.  FP64 keeps 1 - r^2 accurate at the support edge, where the Beta
+// kernel's slope beta (1 - r^2)^(beta - 1) is unbounded for beta < 1.
+__device__ __forceinline__ double eval_r2(double dx, double dy, double a00, double a01x2, double a11)
 {
-    const float t = __fmaf_rn(a01x2, dy, __fmul_rn(a00, dx));
-    return __fmaf_rn(dx, t, __fmul_rn(__fmul_rn(a11, dy), dy));
+    const double t = fma(a01x2, dy, __dmul_rn(a00, dx));
+    return fma(dx, t, __dmul_rn(__dmul_rn(a11, dy), dy));
 }
 
-// alpha before the clamp: o (1 - r^2)^beta via exp2(beta log2(1 - r^2)).
-__device__ __forceinline__ float eval_kernel(float r2, float beta, float *lg)
+// B = (1 - r^2)^beta via exp2(beta log2(1 - r^2)); omr = 1 - r^2 > 0.
+__device__ __forceinline__ float eval_kernel(float omr, float beta, float *lg)
 {
-    const float omr = __fsub_rn(1.0f, r2);
     *lg = __builtin_amdgcn_logf(omr);
     return __builtin_amdgcn_exp2f(__fmul_rn(beta, *lg));
 }
+
+__device__ __forceinline__ float2 unpack2(double d) { return __builtin_bit_cast(float2, d); }
+__device__ __forceinline__ double pack2(float a, float b) { return __builtin_bit_cast(double, make_float2(a, b)); }
 
 __device__ __forceinline__ int find_view(const ViewDesc *views, int32_t n_views, uint32_t g)
 {
@@ -163,36 +167,49 @@ __device__ __forceinline__ float rect_min_r2(float cx, float cy, float a00, floa
     return best;
 }
 
+// LDS image of a staged splat: tile-local centre and conic in FP64, (o, beta)
+// packed in the second half of s_b, colour and the wave mask in s_col.
+struct Staged {
+    double2 *c;    // (cx, cy) relative to the tile origin
+    double2 *a;    // (A00, 2 A01)
+    double2 *b;    // (A11, pack(o, beta))
+    float4 *col;   // (r, g, b, wave mask bits)
+    uint32_t *rec; // record index (reverse pass only)
+};
+
 // Stage records [lo, lo + nb) of the pair list into LDS slot k = j - lo.
 template <int TW, int TH>
-__device__ __forceinline__ void stage(const RasterArgs &a, uint32_t lo, int nb, float fox, float foy, float4 *s_p,
-                                      float4 *s_q, float4 *s_c, int tid)
+__device__ __forceinline__ void stage(const RasterArgs &a, uint32_t lo, int nb, double dox, double doy,
+                                      const Staged &S, int tid)
 {
     using G = Geo<TW, TH>;
     for (int k = tid; k < nb; k += G::NT) {
         const uint32_t rec = a.pair_rec[lo + (uint32_t)k];
-        const float4 c = a.centre[rec], q = a.conic[rec], col = a.color[rec];
-        const float cx = __fadd_rn(__fsub_rn(c.x, fox), c.z), cy = __fadd_rn(__fsub_rn(c.y, foy), c.w);
+        const RasterRec r = a.rec[rec];
+        const double cx = r.cx - dox, cy = r.cy - doy;
         uint32_t mask = 0;
+        const float fcx = (float)cx, fcy = (float)cy, f00 = (float)r.a00, f01 = (float)r.a01, f11 = (float)r.a11;
 #pragma unroll
         for (int w = 0; w < G::NW; ++w) {
             const float bx = (float)((w % G::BX) * 8), by = (float)((w / G::BX) * 8);
-            const float m = rect_min_r2(cx, cy, q.x, q.y, q.z, bx + 0.5f, bx + 7.5f, by + 0.5f, by + 7.5f);
+            const float m = rect_min_r2(fcx, fcy, f00, f01, f11, bx + 0.5f, bx + 7.5f, by + 0.5f, by + 7.5f);
             if (!(m >= 1.0001f)) mask |= 1u << w;
         }
-        s_p[k] = make_float4(cx, cy, q.x, 2.0f * q.y);
-        s_q[k] = make_float4(q.z, q.w, col.w, col.x);
-        s_c[k] = make_float4(col.y, col.z, __uint_as_float(mask), __uint_as_float(rec));
+        S.c[k] = make_double2(cx, cy);
+        S.a[k] = make_double2(r.a00, 2.0 * r.a01);
+        S.b[k] = make_double2(r.a11, pack2(r.opacity, r.beta));
+        S.col[k] = make_float4(r.r, r.g, r.b, __uint_as_float(mask));
+        if (S.rec) S.rec[k] = rec;
     }
 }
 
 // Wave `w` collects, in order, the slots whose mask has bit w.  Returns the count.
-__device__ __forceinline__ int build_list(const float4 *s_c, int nb, int w, uint8_t *list, int lane)
+__device__ __forceinline__ int build_list(const float4 *s_col, int nb, int w, uint8_t *list, int lane)
 {
     int cnt = 0;
     for (int base = 0; base < nb; base += kWave) {
         const int k = base + lane;
-        const bool in = k < nb && ((__float_as_uint(s_c[k].z) >> w) & 1u);
+        const bool in = k < nb && ((__float_as_uint(s_col[k].w) >> w) & 1u);
         const uint64_t bal = __ballot(in);
         if (in) list[cnt + __popcll(bal & ((lane ? (~0ull >> (64 - lane)) : 0ull)))] = (uint8_t)k;
         cnt += __popcll(bal);
@@ -207,14 +224,14 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
 {
     using G = Geo<TW, TH>;
     static_assert(BATCH <= 256, "list entries are 8-bit");
-    __shared__ float4 s_p[BATCH];  // local centre x, y, A00, 2 A01
-    __shared__ float4 s_q[BATCH];  // A11, o, beta, r
-    __shared__ float4 s_c[BATCH];  // g, b, wave mask, record
+    __shared__ double2 s_c[BATCH], s_a[BATCH], s_b[BATCH];
+    __shared__ float4 s_col[BATCH];
     __shared__ uint8_t s_list[G::NW][BATCH];
     __shared__ Item s_item;
+    const Staged S{s_c, s_a, s_b, s_col, nullptr};
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const int lx = (w % G::BX) * 8 + (lane & 7), ly = (w / G::BX) * 8 + (lane >> 3);
-    const float fpx = (float)lx + 0.5f, fpy = (float)ly + 0.5f;
+    const double fpx = (double)lx + 0.5, fpy = (double)ly + 0.5;
 
     for (int iter = 0;; ++iter) {
         if (!fetch_item<TW, TH>(a, &a.queue[0], &s_item, iter)) break;
@@ -225,30 +242,28 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
         bool done = !inside;
         float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
         int32_t last = -1;
-        const float fox = (float)it.ox, foy = (float)it.oy;
 
         for (uint32_t start = it.start; start < it.end; start += BATCH) {
             if (__syncthreads_count(!done) == 0) break;
             const int nb = (int)min((uint32_t)BATCH, it.end - start);
-            stage<TW, TH>(a, start, nb, fox, foy, s_p, s_q, s_c, tid);
+            stage<TW, TH>(a, start, nb, (double)it.ox, (double)it.oy, S, tid);
             __syncthreads();
-            const int cnt = build_list(s_c, nb, w, s_list[w], lane);
+            const int cnt = build_list(s_col, nb, w, s_list[w], lane);
             if (!done) {
                 for (int t = 0; t < cnt; ++t) {
                     const int k = s_list[w][t];
-                    const float4 p = s_p[k];
-                    const float dx = __fsub_rn(fpx, p.x), dy = __fsub_rn(fpy, p.y);
-                    const float4 q = s_q[k];
-                    const float r2 = eval_r2(dx, dy, p.z, p.w, q.x);
-                    if (r2 < 1.0f) {
+                    const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
+                    const double r2 = eval_r2(fpx - c.x, fpy - c.y, aa.x, aa.y, bb.x);
+                    if (r2 < 1.0) {
+                        const float2 ob = unpack2(bb.y);
                         float lg;
-                        const float B = eval_kernel(r2, q.z, &lg);
-                        const float alpha = fminf(a.alpha_max, __fmul_rn(q.y, B));
+                        const float B = eval_kernel((float)(1.0 - r2), ob.y, &lg);
+                        const float alpha = fminf(a.alpha_max, __fmul_rn(ob.x, B));
                         const float wgt = alpha * T;
-                        const float4 cc = s_c[k];
-                        C0 = __fmaf_rn(q.w, wgt, C0);
-                        C1 = __fmaf_rn(cc.x, wgt, C1);
-                        C2 = __fmaf_rn(cc.y, wgt, C2);
+                        const float4 cc = s_col[k];
+                        C0 = __fmaf_rn(cc.x, wgt, C0);
+                        C1 = __fmaf_rn(cc.y, wgt, C1);
+                        C2 = __fmaf_rn(cc.z, wgt, C2);
                         T = __fmul_rn(T, __fsub_rn(1.0f, alpha));
                         last = (int32_t)(start + (uint32_t)k);
                         if (T < a.t_eps) {
@@ -289,16 +304,18 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
     using G = Geo<TW, TH>;
     constexpr int NT = G::NT;
     constexpr int NG = 10;
-    __shared__ float4 s_p[BATCH];
-    __shared__ float4 s_q[BATCH];
-    __shared__ float4 s_c[BATCH];
+    static_assert(BATCH <= 256, "list entries are 8-bit");
+    __shared__ double2 s_c[BATCH], s_a[BATCH], s_b[BATCH];
+    __shared__ float4 s_col[BATCH];
+    __shared__ uint32_t s_rec[BATCH];
     __shared__ float s_g[BATCH][NG];
     __shared__ uint8_t s_list[G::NW][BATCH];
     __shared__ Item s_item;
     __shared__ int32_t s_maxlast;
+    const Staged S{s_c, s_a, s_b, s_col, s_rec};
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const int lx = (w % G::BX) * 8 + (lane & 7), ly = (w / G::BX) * 8 + (lane >> 3);
-    const float fpx = (float)lx + 0.5f, fpy = (float)ly + 0.5f;
+    const double fpx = (double)lx + 0.5, fpy = (double)ly + 0.5;
     const float kLn2 = 0.69314718055994531f;
     // lanes holding the reduced sums (see wave_reduce.h)
     const int row = lane >> 4;
@@ -333,51 +350,51 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
         if (lane == 0 && wave_last >= 0) atomicMax(&s_maxlast, wave_last);
         __syncthreads();
         const int64_t maxlast = s_maxlast;
-        const float fox = (float)it.ox, foy = (float)it.oy;
 
         if (maxlast >= (int64_t)it.start) {
             for (int64_t hi = maxlast + 1; hi > (int64_t)it.start; hi -= BATCH) {
                 const int64_t lo = hi - BATCH > (int64_t)it.start ? hi - BATCH : (int64_t)it.start;
                 const int nb = (int)(hi - lo);
-                stage<TW, TH>(a, (uint32_t)lo, nb, fox, foy, s_p, s_q, s_c, tid);
+                stage<TW, TH>(a, (uint32_t)lo, nb, (double)it.ox, (double)it.oy, S, tid);
                 for (int idx = tid; idx < nb * NG; idx += NT) (&s_g[0][0])[idx] = 0.0f;
                 __syncthreads();
                 // this wave only needs its own splats up to its last contributor
                 const int64_t kmax64 = (int64_t)wave_last - lo;
                 const int nbw = kmax64 < (int64_t)(nb - 1) ? (int)kmax64 + 1 : nb;
-                const int cnt = nbw > 0 ? build_list(s_c, nbw, w, s_list[w], lane) : 0;
+                const int cnt = nbw > 0 ? build_list(s_col, nbw, w, s_list[w], lane) : 0;
                 for (int t = cnt - 1; t >= 0; --t) {
                     const int k = s_list[w][t];
                     const int32_t j = (int32_t)(lo + k);
-                    const float4 p = s_p[k];
-                    const float4 q = s_q[k];
-                    const float dx = __fsub_rn(fpx, p.x), dy = __fsub_rn(fpy, p.y);
-                    const float r2 = eval_r2(dx, dy, p.z, p.w, q.x);
-                    const bool contrib = j <= last && r2 < 1.0f;
+                    const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
+                    const double dxd = fpx - c.x, dyd = fpy - c.y;
+                    const double r2 = eval_r2(dxd, dyd, aa.x, aa.y, bb.x);
+                    const bool contrib = j <= last && r2 < 1.0;
                     if (!__ballot(contrib)) continue;
                     // Branch-free from here: a lane that does not take part uses
-                    // r2 = 0 (finite logs) and alpha = 0 (T, S unchanged), and
+                    // r^2 = 0 (finite logs) and alpha = 0 (T, S unchanged), and
                     // its terms are multiplied by zero.
+                    const float2 ob = unpack2(bb.y);
+                    const float omr = contrib ? (float)(1.0 - r2) : 1.0f;
                     float lg;
-                    const float r2c = contrib ? r2 : 0.0f;
-                    const float B = eval_kernel(r2c, q.z, &lg);
-                    const float araw = __fmul_rn(q.y, B);
+                    const float B = eval_kernel(omr, ob.y, &lg);
+                    const float araw = __fmul_rn(ob.x, B);
                     const bool clamped = araw > a.alpha_max;
                     const float alpha = contrib ? (clamped ? a.alpha_max : araw) : 0.0f;
                     const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
                     const float Ti = T * inv;
                     const float wgt = alpha * Ti;
-                    const float4 cc = s_c[k];
-                    const float gc = g0 * q.w + g1 * cc.x + g2 * cc.y;
+                    const float4 cc = s_col[k];
+                    const float gc = g0 * cc.x + g1 * cc.y + g2 * cc.z;
                     const float gS = g0 * S0 + g1 * S1 + g2 * S2;
                     const float dLda = Ti * gc - inv * gS;
-                    S0 = __fmaf_rn(q.w, wgt, S0);
-                    S1 = __fmaf_rn(cc.x, wgt, S1);
-                    S2 = __fmaf_rn(cc.y, wgt, S2);
+                    S0 = __fmaf_rn(cc.x, wgt, S0);
+                    S1 = __fmaf_rn(cc.y, wgt, S1);
+                    S2 = __fmaf_rn(cc.z, wgt, S2);
                     T = contrib ? Ti : T;
                     // per-splat factors (o, beta, A) are applied once after the sums
                     const float t1 = (contrib && !clamped) ? dLda * B : 0.0f;
-                    const float gp = t1 * __builtin_amdgcn_rcpf(1.0f - r2c);
+                    const float gp = t1 * __builtin_amdgcn_rcpf(omr);
+                    const float dx = (float)dxd, dy = (float)dyd;
                     const float u = gp * dx, wv = gp * dy;
                     float v[NG];
                     v[0] = u;
@@ -399,23 +416,23 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                     }
                 }
                 __syncthreads();
-                // per (tile, splat): apply the per-splat factors and add to the record.
+                // per (tile, splat): apply the per-splat factors.
                 // With gr2 = dL/dr^2 = -o beta g', d = p - mu':
                 //   dL/dmu' = -2 gr2 A d  = 2 o beta A (sum g' d)
                 //   dL/dA   = gr2 d d^T  = -o beta sum g' d d^T
                 //   dL/db   = o beta ln2 sum dLda B log2(1 - r^2)
                 for (int k = tid; k < nb; k += NT) {
                     float *sg = s_g[k];
-                    const float4 p = s_p[k], q = s_q[k];
-                    const float ob = q.y * q.z;
-                    const float a00 = p.z, a01 = 0.5f * p.w, a11 = q.x;
+                    const float2 ob = unpack2(s_b[k].y);
+                    const float obt = ob.x * ob.y;
+                    const float a00 = (float)s_a[k].x, a01 = (float)(0.5 * s_a[k].y), a11 = (float)s_b[k].x;
                     const float su = sg[0], sw = sg[1];
-                    sg[0] = 2.0f * ob * (a00 * su + a01 * sw);
-                    sg[1] = 2.0f * ob * (a01 * su + a11 * sw);
-                    sg[2] *= -ob;
-                    sg[3] *= -ob;
-                    sg[4] *= -ob;
-                    sg[6] *= ob * kLn2;
+                    sg[0] = 2.0f * obt * (a00 * su + a01 * sw);
+                    sg[1] = 2.0f * obt * (a01 * su + a11 * sw);
+                    sg[2] *= -obt;
+                    sg[3] *= -obt;
+                    sg[4] *= -obt;
+                    sg[6] *= obt * kLn2;
                 }
                 __syncthreads();
                 // consecutive lanes take consecutive values of a record: each wave-wide
@@ -423,8 +440,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 for (int idx = tid; idx < nb * NG; idx += NT) {
                     const int k = idx / NG, f = idx - k * NG;
                     const float sg = s_g[k][f];
-                    if (sg != 0.0f)
-                        unsafeAtomicAdd(&a.sgrad[(int64_t)__float_as_uint(s_c[k].w) * 16 + f], sg);
+                    if (sg != 0.0f) unsafeAtomicAdd(&a.sgrad[(int64_t)s_rec[k] * 16 + f], sg);
                 }
                 __syncthreads();
             }
@@ -454,13 +470,12 @@ __global__ __launch_bounds__(TW *TH) void raster_stats_kernel(RasterArgs a, int6
         int32_t last = a.last_index[pix];
         if (last >= (int32_t)r.y) last = (int32_t)r.y - 1;
         const bool stopped = a.final_T[pix] < a.t_eps;
-        const float fpx = (float)(px - ox) + 0.5f, fpy = (float)(py - oy) + 0.5f;
+        const double fpx = (double)(px - ox) + 0.5, fpy = (double)(py - oy) + 0.5;
         for (int32_t j = (int32_t)r.x; j <= last; ++j) {
-            const uint32_t rec = a.pair_rec[j];
-            const float4 c = a.centre[rec], q = a.conic[rec];
-            const float cx = __fadd_rn(__fsub_rn(c.x, (float)ox), c.z), cy = __fadd_rn(__fsub_rn(c.y, (float)oy), c.w);
-            const float r2 = eval_r2(__fsub_rn(fpx, cx), __fsub_rn(fpy, cy), q.x, 2.0f * q.y, q.z);
-            contrib += r2 < 1.0f;
+            const RasterRec rr = a.rec[a.pair_rec[j]];
+            const double r2 = eval_r2(fpx - (rr.cx - (double)ox), fpy - (rr.cy - (double)oy), rr.a00, 2.0 * rr.a01,
+                                      rr.a11);
+            contrib += r2 < 1.0;
         }
         ev = last >= (int32_t)r.x ? (uint64_t)(last - (int32_t)r.x + 1) : 0;
         ev_fwd = stopped ? ev : (uint64_t)(r.y - r.x);
@@ -474,6 +489,62 @@ __global__ __launch_bounds__(TW *TH) void raster_stats_kernel(RasterArgs a, int6
         atomicAdd((unsigned long long *)&out[0], (unsigned long long)ev);
         atomicAdd((unsigned long long *)&out[1], (unsigned long long)contrib);
         atomicAdd((unsigned long long *)&out[2], (unsigned long long)ev_fwd);
+    }
+}
+
+// Wave-level work of the reverse pass, with its exact traversal (staging,
+// culling, per-wave lists): out[3] += list entries walked, out[4] += those
+// with at least one contributing lane.  One workgroup per tile.
+template <int TW, int TH, int BATCH>
+__global__ __launch_bounds__(TW *TH) void raster_wave_stats_kernel(RasterArgs a, int64_t *out)
+{
+    using G = Geo<TW, TH>;
+    __shared__ double2 s_c[BATCH], s_a[BATCH], s_b[BATCH];
+    __shared__ float4 s_col[BATCH];
+    __shared__ uint8_t s_list[G::NW][BATCH];
+    __shared__ int32_t s_maxlast;
+    const Staged S{s_c, s_a, s_b, s_col, nullptr};
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const int lx = (w % G::BX) * 8 + (lane & 7), ly = (w / G::BX) * 8 + (lane >> 3);
+    const double fpx = (double)lx + 0.5, fpy = (double)ly + 0.5;
+    const uint32_t g = blockIdx.x;
+    const int v = find_view(a.views, a.n_views, g);
+    const ViewDesc &V = a.views[v];
+    const uint32_t lt = g - (uint32_t)V.tile_offset;
+    const int ox = (int)(lt % (uint32_t)V.tiles_x) * TW, oy = (int)(lt / (uint32_t)V.tiles_x) * TH;
+    const uint2 rg = a.ranges[g];
+    const int px = ox + lx, py = oy + ly;
+    int32_t last = -1;
+    if (px < V.width && py < V.height) last = a.last_index[V.pixel_offset + (int64_t)py * V.width + px];
+    if (last >= (int32_t)rg.y) last = (int32_t)rg.y - 1;
+    if (tid == 0) s_maxlast = -1;
+    __syncthreads();
+    const int32_t wave_last = wave_max_i32(last);
+    if (lane == 0 && wave_last >= 0) atomicMax(&s_maxlast, wave_last);
+    __syncthreads();
+    const int64_t maxlast = s_maxlast;
+    uint64_t walked = 0, active = 0;
+    for (int64_t hi = maxlast + 1; hi > (int64_t)rg.x; hi -= BATCH) {
+        const int64_t lo = hi - BATCH > (int64_t)rg.x ? hi - BATCH : (int64_t)rg.x;
+        const int nb = (int)(hi - lo);
+        stage<TW, TH>(a, (uint32_t)lo, nb, (double)ox, (double)oy, S, tid);
+        __syncthreads();
+        const int64_t kmax64 = (int64_t)wave_last - lo;
+        const int nbw = kmax64 < (int64_t)(nb - 1) ? (int)kmax64 + 1 : nb;
+        const int cnt = nbw > 0 ? build_list(s_col, nbw, w, s_list[w], lane) : 0;
+        for (int t = cnt - 1; t >= 0; --t) {
+            const int k = s_list[w][t];
+            const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
+            const double r2 = eval_r2(fpx - c.x, fpy - c.y, aa.x, aa.y, bb.x);
+            const bool contrib = (int32_t)(lo + k) <= last && r2 < 1.0;
+            walked += 1;
+            active += __ballot(contrib) != 0;
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        atomicAdd((unsigned long long *)&out[3], (unsigned long long)walked);
+        atomicAdd((unsigned long long *)&out[4], (unsigned long long)active);
     }
 }
 
@@ -541,9 +612,7 @@ RasterArgs make_args(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t n_tiles, c
     a.views = P.views;
     a.n_views = n_views;
     a.n_tiles = (uint32_t)n_tiles;
-    a.centre = P.centre;
-    a.conic = P.conic;
-    a.color = P.color;
+    a.rec = P.rec;
     a.pair_rec = B.pair_rec;
     a.ranges = B.tile_range;
     a.order = B.tile_order;
@@ -609,12 +678,17 @@ hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t 
     a.last_index = (int32_t *)last_index;
     const int tw = cfg.tile_w, th = cfg.tile_h;
     const dim3 grid((unsigned)n_tiles), block((unsigned)(tw * th));
-    if (tw == 16 && th == 16) raster_stats_kernel<16, 16><<<grid, block, 0, s>>>(a, out);
-    else if (tw == 16 && th == 8) raster_stats_kernel<16, 8><<<grid, block, 0, s>>>(a, out);
-    else if (tw == 8 && th == 8) raster_stats_kernel<8, 8><<<grid, block, 0, s>>>(a, out);
-    else if (tw == 32 && th == 8) raster_stats_kernel<32, 8><<<grid, block, 0, s>>>(a, out);
-    else if (tw == 32 && th == 16) raster_stats_kernel<32, 16><<<grid, block, 0, s>>>(a, out);
-    else return hipErrorInvalidValue;
+#define DBS_STATS(TW, TH)                                                                     \
+    if (tw == TW && th == TH) {                                                               \
+        raster_stats_kernel<TW, TH><<<grid, block, 0, s>>>(a, out);                          \
+        if (cfg.batch == 64) raster_wave_stats_kernel<TW, TH, 64><<<grid, block, 0, s>>>(a, out);   \
+        else if (cfg.batch == 128) raster_wave_stats_kernel<TW, TH, 128><<<grid, block, 0, s>>>(a, out); \
+        else raster_wave_stats_kernel<TW, TH, 256><<<grid, block, 0, s>>>(a, out);            \
+        return hipGetLastError();                                                             \
+    }
+    DBS_STATS(16, 16) DBS_STATS(16, 8) DBS_STATS(8, 8) DBS_STATS(32, 8) DBS_STATS(32, 16)
+#undef DBS_STATS
+    return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -169,13 +169,14 @@ class Rasterizer:
 
     def stats(self, final_T, last) -> dict:
         """Evaluated / contributing (pixel, pair) counts of the last forward."""
-        out = torch.zeros(3, dtype=torch.int64, device=self.device)
+        out = torch.zeros(5, dtype=torch.int64, device=self.device)
         check("dbs_render_stats", self.lib.dbs_render_stats(
             C.c_void_p(self.projected.data_ptr()), C.c_void_p(self.bins.data_ptr()), self.cams_c, self.V,
             C.byref(self.cfg_c), self.n, C.c_void_p(final_T.data_ptr()), C.c_void_p(last.data_ptr()),
             C.c_void_p(out.data_ptr()), _stream()))
         o = out.cpu().tolist()
-        return {"bwd_evaluated": o[0], "contributing": o[1], "fwd_evaluated": o[2]}
+        return {"bwd_evaluated": o[0], "contributing": o[1], "fwd_evaluated": o[2],
+                "bwd_wave_entries": o[3], "bwd_wave_entries_active": o[4]}
 
     # ---- eager helpers ----
     def forward(self, params: dict, outputs=None):
@@ -213,23 +214,25 @@ class Rasterizer:
     # ---- introspection ----
     def records(self) -> dict:
         """Per-record arrays (record r = v n + i) viewed from `projected`."""
-        ptrs = [C.c_void_p() for _ in range(7)]
+        ptrs = [C.c_void_p() for _ in range(5)]
         check("dbs_projected_layout", self.lib.dbs_projected_layout(
             C.c_void_p(self.projected.data_ptr()), self.n, self.V, *[C.byref(p) for p in ptrs]))
         base = self.projected.data_ptr()
         R = self.n * self.V
 
-        def sl(p, nbytes, dtype, shape):
+        def sl(p, nbytes):
             off = (p.value or base) - base
-            return self.projected[off:off + nbytes].view(dtype).view(*shape)
+            return self.projected[off:off + nbytes]
 
-        return dict(centre=sl(ptrs[0], 16 * R, torch.float32, (R, 4)),
-                    conic=sl(ptrs[1], 16 * R, torch.float32, (R, 4)),
-                    color=sl(ptrs[2], 16 * R, torch.float32, (R, 4)),
-                    bbox=sl(ptrs[3], 8 * R, torch.int16, (R, 4)),
-                    depth=sl(ptrs[4], 4 * R, torch.int32, (R,)),
-                    ntiles=sl(ptrs[5], 4 * R, torch.int32, (R,)),
-                    counts=sl(ptrs[6], 16, torch.int64, (2,)))
+        rec = sl(ptrs[0], 64 * R)
+        f64 = rec.view(torch.float64).view(R, 8)
+        f32 = rec.view(torch.float32).view(R, 16)
+        return dict(centre=f64[:, 0:2], conic=f64[:, 2:5], opacity=f32[:, 10], beta=f32[:, 11],
+                    color=f32[:, 12:15],
+                    bbox=sl(ptrs[1], 8 * R).view(torch.int16).view(R, 4),
+                    depth=sl(ptrs[2], 4 * R).view(torch.int32).view(R),
+                    ntiles=sl(ptrs[3], 4 * R).view(torch.int32).view(R),
+                    counts=sl(ptrs[4], 16).view(torch.int64).view(2))
 
     def bins_arrays(self) -> dict:
         ptrs = [C.c_void_p() for _ in range(3)]

@@ -1,0 +1,128 @@
+"""Batched path at the benchmark's sizes and launch configuration: graph
+replay equals eager, sampled pixels and tiles of configs 2 and 3 against the
+oracle, a crop-restricted gradient at full scene size.  Needs an MI355X."""
+import numpy as np
+import pytest
+
+from paper_2501_18630_amd import scenes
+from gpu_helpers import AMAX, TEPS, PARAMS, assert_grads_close, assert_image_close, hw3
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def config3():
+    return scenes.config3()
+
+
+def _pixels(rng, w, h, k):
+    return np.stack([rng.integers(0, w, k), rng.integers(0, h, k)], 1).astype(np.int32)
+
+
+def test_graph_replay_equals_eager():
+    import torch
+    from paper_2501_18630_amd import renderer
+    s = scenes.uniform_box_scene(3000, [-2, -2, 2], [2, 2, 8], m=2, seed=31)
+    cams = [scenes.look_at_camera(p, w, h) for p, (w, h) in
+            zip([[0, 0, -9.0], [4.0, 1.0, -7.0], [-3.0, 3.0, -6.0]], [(96, 64), (80, 80), (65, 97)])]
+    params = renderer.to_device(s)
+    targets = torch.as_tensor(np.random.default_rng(2).uniform(0, 1, 3 * sum(
+        c["width"] * c["height"] for c in cams)).astype(np.float32)).cuda()
+    eager = renderer.TrainStep(renderer.Rasterizer(cams, 3000, 2), params, targets, use_graph=False)
+    eager.run()
+    torch.cuda.synchronize()
+    ref_img = eager.image.clone()
+    ref_g = {k: v.clone() for k, v in eager.grads.items()}
+    graph = renderer.TrainStep(renderer.Rasterizer(cams, 3000, 2), params, targets, use_graph=True)
+    for rep in range(4):
+        graph.run()
+        # eager work on the same stream between replays
+        scratch = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert not graph.overflowed()
+        assert torch.equal(graph.image, ref_img), rep
+        for k in PARAMS:
+            torch.testing.assert_close(graph.grads[k], ref_g[k], rtol=1e-5, atol=1e-8)
+        del scratch
+
+
+def test_graph_overflow_is_reported():
+    import torch
+    from paper_2501_18630_amd import renderer
+    s = scenes.uniform_box_scene(2000, [-2, -2, 2], [2, 2, 8], m=2, seed=32)
+    cams = [scenes.camera(64, 48, f=64.0)]
+    params = renderer.to_device(s)
+    target = torch.zeros(3 * 64 * 48, device="cuda")
+    step = renderer.TrainStep(renderer.Rasterizer(cams, 2000, 2), params, target, headroom=1.0)
+    step.run()
+    assert not step.overflowed()
+    params["scales"].mul_(3.0)  # larger supports -> more pairs than captured capacity
+    step.run()
+    torch.cuda.synchronize()
+    assert step.overflowed()
+    assert torch.all(step.final_T == 1.0)
+
+
+@pytest.mark.parametrize("which", [2, 3])
+def test_fullsize_sampled_pixels(oracle, config3, which):
+    """Forward at full size in the benchmark's launch configuration (batched,
+    persistent, 16x16, batch 256); sampled pixels against the oracle."""
+    from gpu_helpers import gpu_render
+    s, cams = scenes.config2() if which == 2 else config3
+    views = [0] if which == 2 else [0, 7, 15]
+    out = gpu_render(s, cams)
+    rng = np.random.default_rng(11)
+    for v in views:
+        cam = cams[v]
+        pix = _pixels(rng, cam["width"], cam["height"], 48)
+        ref = oracle.render(s, cam, float(AMAX), float(TEPS), pixels=pix)
+        gpu = out["images"][v][:, pix[:, 1], pix[:, 0]].T
+        assert_image_close(gpu, ref["rgb"], ref["T"], ref["T_prev"])
+
+
+def test_fullsize_sampled_tiles_bit_exact(oracle, config3):
+    from gpu_helpers import gpu_render
+    s, cams = config3
+    n = s["means"].shape[0]
+    out = gpu_render(s, cams)
+    rast = out["rast"]
+    rec = {k: v.cpu().numpy() for k, v in rast.records().items()}
+    b = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in rast.bins_arrays().items()}
+    toff = rast.tile_offsets()
+    rng = np.random.default_rng(12)
+    for v in (0, 5, 15):
+        cam = cams[v]
+        sl = slice(v * n, (v + 1) * n)
+        nt = int(toff[v + 1] - toff[v])
+        tiles = rng.integers(0, nt, 6)
+        st, ids = oracle.bin_tiles((rec["ntiles"][sl] > 0).astype(np.int32), rec["bbox"][sl].astype(np.int32),
+                                   rec["depth"][sl].view(np.uint32), cam["width"], 16, 16, tiles)
+        for r, t in enumerate(tiles):
+            lo, hi = b["tile_range"][toff[v] + t]
+            got = b["pair_rec"][lo:hi].astype(np.int64) - v * n
+            np.testing.assert_array_equal(got, ids[st[r]:st[r + 1]])
+
+
+def test_fullsize_crop_gradient_batched(oracle, config3):
+    """Batched backward over all 16 views with dL/dimage non-zero only on a
+    48x48 crop of one view: the gradient of every splat matches the oracle
+    on that crop (splats that cannot reach it get exactly zero)."""
+    from gpu_helpers import gpu_render
+    s, cams = config3
+    v0, x0, y0, w = 3, 300, 200, 48
+    dls = [np.zeros((3, c["height"], c["width"]), np.float32) for c in cams]
+    crop = np.random.default_rng(13).standard_normal((3, w, w)).astype(np.float32)
+    dls[v0][:, y0:y0 + w, x0:x0 + w] = crop
+    out = gpu_render(s, cams, grads_from=dls)
+    cam = cams[v0]
+    p = oracle.project(s, cam)
+    bb = p["bbox"]
+    near = np.where((p["valid"] == 1) & (bb[:, 0] <= x0 + w - 1) & (bb[:, 1] >= x0) & (bb[:, 2] <= y0 + w - 1)
+                    & (bb[:, 3] >= y0) & (bb[:, 0] <= bb[:, 1]) & (bb[:, 2] <= bb[:, 3]))[0]
+    assert near.size > 50
+    g, a = oracle.render_bwd(scenes.subset(s, near), cam, float(AMAX), float(TEPS), hw3(crop),
+                             pixels=oracle.crop_pixels(x0, y0, w, w), want_abs=True)
+    assert_grads_close({k: out["grads"][k][near] for k in PARAMS}, g, a)
+    far = np.setdiff1d(np.arange(s["means"].shape[0]), near)
+    for k in PARAMS:
+        assert not np.any(out["grads"][k][far]), k
