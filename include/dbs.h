@@ -96,8 +96,8 @@ typedef struct {
 } dbs_camera;
 
 /* Rasterisation settings.  The built tile shapes are 16x16, 16x8, 8x8, 32x8
- * and 32x16 pixels; batch is the number of splats staged in LDS per step
- * (64, 128 or 256, and a multiple of tile_w * tile_h or a divisor of it).
+ * and 32x16 pixels; batch is the number of splats the forward pass stages
+ * in LDS at a time (64, 128 or 256; the reverse pass stages min(batch, 128)).
  * A splat contributes alpha = min(alpha_max, o B(r^2; b)) where r^2 < 1; a
  * pixel stops after the splat that takes its transmittance below t_eps. */
 typedef struct {
@@ -207,9 +207,11 @@ dbs_status dbs_project_bwd(const dbs_splats *splats /*[host] struct of device po
  * out[1] += those with r^2 < 1 (the pairs composited by Eq. 6);
  * out[2] += evaluations of the forward: list positions from the start to the
  *           pixel's last_index, or to the list end if it never stopped;
- * out[3] += (wavefront, splat) list entries the reverse pass walks after its
- *           per-8x8-block culling;
- * out[4] += those entries in which at least one pixel has r^2 < 1.
+ * out[3] += wavefront steps of the reverse pass: each wavefront covers an
+ *           8x8 pixel block, each of its four 16-lane rows a 4x4 quadrant
+ *           that walks its own culled list, and a step takes one entry of
+ *           every row's list;
+ * out[4] += those steps in which at least one pixel has r^2 < 1.
  * out: device int64[5], accumulated. */
 dbs_status dbs_render_stats(const void *projected, const void *bins, const dbs_camera *cams /*[host]*/,
                             int32_t n_views, const dbs_raster_cfg *cfg /*[host]*/, int64_t n,

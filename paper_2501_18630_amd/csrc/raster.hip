@@ -19,13 +19,15 @@
 //   dL/dmu' = -2 dL/dr^2 A d,   dL/dA = dL/dr^2 d d^T.
 // The per-pixel terms are summed without their per-splat factors (o, beta,
 // A), which are applied once per (tile, splat) before the global atomics.
-// The ten per-(pixel, splat) values are summed over each wavefront with a
-// permlane/DPP butterfly (wave_reduce.h), then over the workgroup with LDS
-// float atomics, then added once per (tile, splat) to the per-record
-// screen-space gradient with a global float atomic.
+// The ten per-(pixel, splat) values are summed over each 16-lane row with a
+// DPP halving butterfly (wave_reduce.h), added into per-wavefront LDS slots
+// (plain read-add-write: LDS float atomics cost about a cycle per lane), summed
+// over the wavefronts once per batch, and added once per (tile, splat) to the
+// per-record screen-space gradient with a global float atomic.
 //
-// Each wavefront owns an 8x8 pixel block and walks only the splats whose
-// support can reach it (see `stage`).
+// Each wavefront owns an 8x8 pixel block, each 16-lane row of it a 4x4
+// quadrant, and every row walks only the splats whose support can reach its
+// quadrant (see `stage`).
 //
 // Work items are (view, tile) pairs.  A persistent grid drains a device
 // queue ordered heaviest tile first; the last workgroup to finish resets the
@@ -131,13 +133,20 @@ __device__ __forceinline__ void finish_persistent(const RasterArgs &a, uint32_t 
 
 // ---------------------------------------------------------------- staging
 //
-// Pixels are assigned so that each wavefront covers one 8x8 block of the tile
-// (block w at ((w % (TW/8)) * 8, (w / (TW/8)) * 8)).  When a batch of splats is
-// staged in LDS, the staging thread computes, for every block, the minimum
-// of r^2 over the block's pixel-centre rectangle; a block whose minimum is
-// at least 1 + 1e-4 cannot have a pixel with r^2 < 1 under FP32 rounding of
-// the per-pixel evaluation, so the splat is left out of that wave's list.
-// The lists change which (pixel, splat) pairs are evaluated, never a result.
+// Each wavefront covers one 8x8 block of the tile (block w at
+// ((w % (TW/8)) * 8, (w / (TW/8)) * 8)); each 16-lane row of a wavefront covers
+// one 4x4 quadrant of its block (row r at ((r & 1) * 4, (r >> 1) * 4)), and
+// lane i of a row the pixel (i & 3, i >> 2) of its quadrant.
+//
+// Culling in two levels.  When a batch of splats is staged in LDS, the staging
+// thread computes, for every block, the minimum of r^2 over the block's
+// pixel-centre rectangle.  Each wavefront then compacts the splats that reach
+// its block and tests its four quadrants the same way for those.  A rectangle
+// whose minimum is at least 1 + 1e-4 cannot hold a pixel with r^2 < 1 (the FP32
+// rounding of the minimum is far below that margin), so the splat is left out
+// of that list.  Each row walks its own list; the four rows of a wavefront
+// step through their lists together.  The lists change which (pixel, splat)
+// pairs are evaluated, never a result.
 
 template <int TW, int TH>
 struct Geo {
@@ -145,6 +154,20 @@ struct Geo {
     static constexpr int NW = NT / kWave;  // waves = 8x8 blocks
     static constexpr int BX = TW / 8;
     static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 blocks");
+};
+
+// Tile-local pixel of a lane: block of wave w, quadrant of row lane/16.
+template <int TW, int TH>
+struct LanePixel {
+    int bx, by, row, lx, ly;
+    __device__ LanePixel(int w, int lane)
+    {
+        bx = (w % Geo<TW, TH>::BX) * 8;
+        by = (w / Geo<TW, TH>::BX) * 8;
+        row = lane >> 4;
+        lx = bx + (row & 1) * 4 + (lane & 3);
+        ly = by + (row >> 1) * 4 + ((lane >> 2) & 3);
+    }
 };
 
 // min over p in [x0,x1] x [y0,y1] of (p - c)^T A (p - c), A positive definite
@@ -168,12 +191,12 @@ __device__ __forceinline__ float rect_min_r2(float cx, float cy, float a00, floa
 }
 
 // LDS image of a staged splat: tile-local centre and conic in FP64, (o, beta)
-// packed in the second half of s_b, colour and the wave mask in s_col.
+// packed in the second half of s_b, colour and the block mask in s_col.
 struct Staged {
     double2 *c;    // (cx, cy) relative to the tile origin
     double2 *a;    // (A00, 2 A01)
     double2 *b;    // (A11, pack(o, beta))
-    float4 *col;   // (r, g, b, wave mask bits)
+    float4 *col;   // (r, g, b, block mask bits)
     uint32_t *rec; // record index (reverse pass only)
 };
 
@@ -203,7 +226,9 @@ __device__ __forceinline__ void stage(const RasterArgs &a, uint32_t lo, int nb, 
     }
 }
 
-// Wave `w` collects, in order, the slots whose mask has bit w.  Returns the count.
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
+
+// Wave `w` collects, in order, the slots [0, nb) whose block mask has bit w.
 __device__ __forceinline__ int build_list(const float4 *s_col, int nb, int w, uint8_t *list, int lane)
 {
     int cnt = 0;
@@ -211,10 +236,73 @@ __device__ __forceinline__ int build_list(const float4 *s_col, int nb, int w, ui
         const int k = base + lane;
         const bool in = k < nb && ((__float_as_uint(s_col[k].w) >> w) & 1u);
         const uint64_t bal = __ballot(in);
-        if (in) list[cnt + __popcll(bal & ((lane ? (~0ull >> (64 - lane)) : 0ull)))] = (uint8_t)k;
+        if (in) list[cnt + __popcll(bal & lanes_below(lane))] = (uint8_t)k;
         cnt += __popcll(bal);
     }
     return cnt;
+}
+
+// Splits a wave's block list into the lists of its four rows (quadrants), in
+// order: slot k goes to row r if its support reaches the quadrant and its list
+// position lo + k is at most lim[r].  rows: [4][BATCH]; counts returned in cnt.
+template <int BATCH>
+__device__ __forceinline__ void build_rows(const Staged &S, const uint8_t *blist, int cnt_b, int bx, int by,
+                                           int64_t lo, const int32_t lim[4], uint8_t *rows, int cnt[4], int lane)
+{
+    cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
+    for (int base = 0; base < cnt_b; base += kWave) {
+        const int e = base + lane;
+        const bool valid = e < cnt_b;
+        const int k = valid ? blist[e] : 0;
+        const double2 c = S.c[k], aa = S.a[k], bb = S.b[k];
+        const float fcx = (float)c.x, fcy = (float)c.y;
+        const float f00 = (float)aa.x, f01 = (float)(0.5 * aa.y), f11 = (float)bb.x;
+        const int32_t j = (int32_t)(lo + k);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float x0 = (float)(bx + (r & 1) * 4) + 0.5f, y0 = (float)(by + (r >> 1) * 4) + 0.5f;
+            const bool in = valid && j <= lim[r] &&
+                            !(rect_min_r2(fcx, fcy, f00, f01, f11, x0, x0 + 3.0f, y0, y0 + 3.0f) >= 1.0001f);
+            const uint64_t bal = __ballot(in);
+            if (in) rows[r * BATCH + cnt[r] + __popcll(bal & lanes_below(lane))] = (uint8_t)k;
+            cnt[r] += __popcll(bal);
+        }
+    }
+}
+
+__device__ __forceinline__ int pick4(const int v[4], int r)
+{
+    return r == 0 ? v[0] : (r == 1 ? v[1] : (r == 2 ? v[2] : v[3]));
+}
+
+__device__ __forceinline__ int max4(const int v[4]) { return max(max(v[0], v[1]), max(v[2], v[3])); }
+
+// Reverse walk: at step s row r takes entry cnt[r] - 1 - s of its list.  Rows
+// that take the same splat at the same step would add to the same LDS slot, so
+// their sums are merged first and only the lowest such row stores.  Nibble r of
+// share[s]: bit 0/1/2 = row r's splat is also that of row r^1 / r^2 / r^3,
+// bit 3 = another, lower row stores for row r.
+template <int BATCH>
+__device__ __forceinline__ void mark_shared_steps(const uint8_t *rows, const int cnt[4], int steps, uint16_t *share,
+                                                  int lane)
+{
+    for (int s0 = 0; s0 < steps; s0 += kWave) {
+        const int st = s0 + lane;
+        int kk[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int t = cnt[r] - 1 - st;
+            kk[r] = (st < steps && t >= 0) ? (int)rows[r * BATCH + t] : -1 - r;
+        }
+        uint32_t word = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool e1 = kk[r] == kk[r ^ 1], e2 = kk[r] == kk[r ^ 2], e3 = kk[r] == kk[r ^ 3];
+            const bool below = (e1 && (r ^ 1) < r) || (e2 && (r ^ 2) < r) || (e3 && (r ^ 3) < r);
+            word |= (uint32_t)(e1 | (e2 << 1) | (e3 << 2) | (below << 3)) << (4 * r);
+        }
+        if (st < steps) share[st] = (uint16_t)word;
+    }
 }
 
 // ---------------------------------------------------------------- forward
@@ -226,18 +314,20 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
     static_assert(BATCH <= 256, "list entries are 8-bit");
     __shared__ double2 s_c[BATCH], s_a[BATCH], s_b[BATCH];
     __shared__ float4 s_col[BATCH];
-    __shared__ uint8_t s_list[G::NW][BATCH];
+    __shared__ uint8_t s_blist[G::NW][BATCH];
+    __shared__ uint8_t s_rows[G::NW][4 * BATCH];
     __shared__ Item s_item;
     const Staged S{s_c, s_a, s_b, s_col, nullptr};
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-    const int lx = (w % G::BX) * 8 + (lane & 7), ly = (w / G::BX) * 8 + (lane >> 3);
-    const double fpx = (double)lx + 0.5, fpy = (double)ly + 0.5;
+    const LanePixel<TW, TH> P(w, lane);
+    const double fpx = (double)P.lx + 0.5, fpy = (double)P.ly + 0.5;
+    const uint8_t *my_row = &s_rows[w][P.row * BATCH];
 
     for (int iter = 0;; ++iter) {
         if (!fetch_item<TW, TH>(a, &a.queue[0], &s_item, iter)) break;
         const Item it = s_item;
         const ViewDesc &V = a.views[it.v];
-        const int px = it.ox + lx, py = it.oy + ly;
+        const int px = it.ox + P.lx, py = it.oy + P.ly;
         const bool inside = px < V.width && py < V.height;
         bool done = !inside;
         float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
@@ -248,29 +338,34 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
             const int nb = (int)min((uint32_t)BATCH, it.end - start);
             stage<TW, TH>(a, start, nb, (double)it.ox, (double)it.oy, S, tid);
             __syncthreads();
-            const int cnt = build_list(s_col, nb, w, s_list[w], lane);
-            if (!done) {
-                for (int t = 0; t < cnt; ++t) {
-                    const int k = s_list[w][t];
-                    const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
-                    const double r2 = eval_r2(fpx - c.x, fpy - c.y, aa.x, aa.y, bb.x);
-                    if (r2 < 1.0) {
-                        const float2 ob = unpack2(bb.y);
-                        float lg;
-                        const float B = eval_kernel((float)(1.0 - r2), ob.y, &lg);
-                        const float alpha = fminf(a.alpha_max, __fmul_rn(ob.x, B));
-                        const float wgt = alpha * T;
-                        const float4 cc = s_col[k];
-                        C0 = __fmaf_rn(cc.x, wgt, C0);
-                        C1 = __fmaf_rn(cc.y, wgt, C1);
-                        C2 = __fmaf_rn(cc.z, wgt, C2);
-                        T = __fmul_rn(T, __fsub_rn(1.0f, alpha));
-                        last = (int32_t)(start + (uint32_t)k);
-                        if (T < a.t_eps) {
-                            done = true;
-                            break;
-                        }
-                    }
+            // rows whose pixels have all stopped take no entries
+            const uint64_t live = __ballot(!done);
+            int32_t lim[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lim[r] = ((live >> (16 * r)) & 0xffffull) ? INT32_MAX : -1;
+            const int cnt_b = live ? build_list(s_col, nb, w, s_blist[w], lane) : 0;
+            int cnt[4];
+            build_rows<BATCH>(S, s_blist[w], cnt_b, P.bx, P.by, (int64_t)start, lim, s_rows[w], cnt, lane);
+            const int my_cnt = pick4(cnt, P.row), steps = max4(cnt);
+            for (int t = 0; t < steps; ++t) {
+                const bool act = t < my_cnt && !done;
+                if (!__ballot(act)) break;
+                const int k = act ? my_row[t] : 0;
+                const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
+                const double r2 = eval_r2(fpx - c.x, fpy - c.y, aa.x, aa.y, bb.x);
+                if (act && r2 < 1.0) {
+                    const float2 ob = unpack2(bb.y);
+                    float lg;
+                    const float B = eval_kernel((float)(1.0 - r2), ob.y, &lg);
+                    const float alpha = fminf(a.alpha_max, __fmul_rn(ob.x, B));
+                    const float wgt = alpha * T;
+                    const float4 cc = s_col[k];
+                    C0 = __fmaf_rn(cc.x, wgt, C0);
+                    C1 = __fmaf_rn(cc.y, wgt, C1);
+                    C2 = __fmaf_rn(cc.z, wgt, C2);
+                    T = __fmul_rn(T, __fsub_rn(1.0f, alpha));
+                    last = (int32_t)(start + (uint32_t)k);
+                    done = T < a.t_eps;
                 }
             }
         }
@@ -298,6 +393,15 @@ __device__ __forceinline__ int wave_max_i32(int v)
     return v;
 }
 
+// Per-row (16-lane) maxima of v, as four wave-uniform values.
+__device__ __forceinline__ void row_max4_i32(int v, int out[4])
+{
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 16));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[r] = __builtin_amdgcn_readlane(v, 16 * r);
+}
+
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
 {
@@ -308,25 +412,25 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
     __shared__ double2 s_c[BATCH], s_a[BATCH], s_b[BATCH];
     __shared__ float4 s_col[BATCH];
     __shared__ uint32_t s_rec[BATCH];
-    __shared__ float s_g[BATCH][NG];
-    __shared__ uint8_t s_list[G::NW][BATCH];
+    __shared__ float s_g[G::NW][BATCH][NG];  // per-wave sums; wave 0's slot ends up with the total
+    __shared__ uint8_t s_blist[G::NW][BATCH];
+    __shared__ uint8_t s_rows[G::NW][4 * BATCH];
+    __shared__ uint16_t s_share[G::NW][BATCH];
     __shared__ Item s_item;
     __shared__ int32_t s_maxlast;
     const Staged S{s_c, s_a, s_b, s_col, s_rec};
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-    const int lx = (w % G::BX) * 8 + (lane & 7), ly = (w / G::BX) * 8 + (lane >> 3);
-    const double fpx = (double)lx + 0.5, fpy = (double)ly + 0.5;
+    const LanePixel<TW, TH> P(w, lane);
+    const double fpx = (double)P.lx + 0.5, fpy = (double)P.ly + 0.5;
+    const uint8_t *my_row = &s_rows[w][P.row * BATCH];
     const float kLn2 = 0.69314718055994531f;
-    // lanes holding the reduced sums (see wave_reduce.h)
-    const int row = lane >> 4;
-    const bool holder = (lane & 15) == 0;
-    const int f0 = reduce10_field0(row);
+    const int fld = row10_field(lane);  // value whose row total this lane stores
 
     for (int iter = 0;; ++iter) {
         if (!fetch_item<TW, TH>(a, &a.queue[2], &s_item, iter)) break;
         const Item it = s_item;
         const ViewDesc &V = a.views[it.v];
-        const int px = it.ox + lx, py = it.oy + ly;
+        const int px = it.ox + P.lx, py = it.oy + P.ly;
         const bool inside = px < V.width && py < V.height;
         const int64_t npx = (int64_t)V.width * V.height;
         const int64_t pl = (int64_t)py * V.width + px;
@@ -347,6 +451,8 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
         if (tid == 0) s_maxlast = -1;
         __syncthreads();
         const int32_t wave_last = wave_max_i32(last);
+        int32_t row_last[4];
+        row_max4_i32(last, row_last);
         if (lane == 0 && wave_last >= 0) atomicMax(&s_maxlast, wave_last);
         __syncthreads();
         const int64_t maxlast = s_maxlast;
@@ -356,19 +462,31 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 const int64_t lo = hi - BATCH > (int64_t)it.start ? hi - BATCH : (int64_t)it.start;
                 const int nb = (int)(hi - lo);
                 stage<TW, TH>(a, (uint32_t)lo, nb, (double)it.ox, (double)it.oy, S, tid);
-                for (int idx = tid; idx < nb * NG; idx += NT) (&s_g[0][0])[idx] = 0.0f;
+                for (int idx = tid; idx < G::NW * BATCH * NG; idx += NT) (&s_g[0][0][0])[idx] = 0.0f;
                 __syncthreads();
                 // this wave only needs its own splats up to its last contributor
                 const int64_t kmax64 = (int64_t)wave_last - lo;
                 const int nbw = kmax64 < (int64_t)(nb - 1) ? (int)kmax64 + 1 : nb;
-                const int cnt = nbw > 0 ? build_list(s_col, nbw, w, s_list[w], lane) : 0;
-                for (int t = cnt - 1; t >= 0; --t) {
-                    const int k = s_list[w][t];
+                const int cnt_b = nbw > 0 ? build_list(s_col, nbw, w, s_blist[w], lane) : 0;
+                int cnt[4];
+                build_rows<BATCH>(S, s_blist[w], cnt_b, P.bx, P.by, lo, row_last, s_rows[w], cnt, lane);
+                const int my_cnt = pick4(cnt, P.row), steps = max4(cnt);
+                mark_shared_steps<BATCH>(s_rows[w], cnt, steps, s_share[w], lane);
+                for (int step = 0; step < steps; ++step) {
+                    const int t = my_cnt - 1 - step;  // back to front
+                    const bool has = t >= 0;
+                    const int kl = my_row[has ? t : 0];  // in bounds either way
+                    const int k = has ? kl : 0;
                     const int32_t j = (int32_t)(lo + k);
+                    const bool owner = fld >= 0 && has;
+                    float *dst = &s_g[w][k][fld < 0 ? 0 : fld];
+                    // read early: the slot's running sum, added to at the end of the step
+                    const float prev = owner ? *dst : 0.0f;
+                    const uint32_t share = s_share[w][step];
                     const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
                     const double dxd = fpx - c.x, dyd = fpy - c.y;
                     const double r2 = eval_r2(dxd, dyd, aa.x, aa.y, bb.x);
-                    const bool contrib = j <= last && r2 < 1.0;
+                    const bool contrib = has && j <= last && r2 < 1.0;
                     if (!__ballot(contrib)) continue;
                     // Branch-free from here: a lane that does not take part uses
                     // r^2 = 0 (finite logs) and alpha = 0 (T, S unchanged), and
@@ -407,13 +525,16 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                     v[7] = g0 * wgt;
                     v[8] = g1 * wgt;
                     v[9] = g2 * wgt;
-                    float o[3];
-                    wave_reduce10(v, o);
-                    if (holder) {
-                        atomicAdd(&s_g[k][f0], o[0]);
-                        atomicAdd(&s_g[k][f0 + 4], o[1]);
-                        if ((row & 1) == 0) atomicAdd(&s_g[k][8 + (row >> 1)], o[2]);
+                    float tot = row_reduce10(v, lane);
+                    // A row holds a splat at most once in its list: only rows taking the
+                    // same splat in this step share a slot.  Merge theirs, lowest stores.
+                    const uint32_t nib = share >> (4 * P.row);
+                    if (share & 0x7777u) {
+                        const float x2 = from_row_xor2(tot, P.row);
+                        const float x1 = from_row_xor1(tot, P.row), x3 = from_row_xor1(x2, P.row);
+                        tot += ((nib & 1u) ? x1 : 0.0f) + ((nib & 2u) ? x2 : 0.0f) + ((nib & 4u) ? x3 : 0.0f);
                     }
+                    if (owner && !(nib & 8u)) *dst = prev + tot;
                 }
                 __syncthreads();
                 // per (tile, splat): apply the per-splat factors.
@@ -422,7 +543,11 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 //   dL/dA   = gr2 d d^T  = -o beta sum g' d d^T
                 //   dL/db   = o beta ln2 sum dLda B log2(1 - r^2)
                 for (int k = tid; k < nb; k += NT) {
-                    float *sg = s_g[k];
+                    float *sg = s_g[0][k];
+#pragma unroll
+                    for (int wv = 1; wv < G::NW; ++wv)
+#pragma unroll
+                        for (int f = 0; f < NG; ++f) sg[f] += s_g[wv][k][f];
                     const float2 ob = unpack2(s_b[k].y);
                     const float obt = ob.x * ob.y;
                     const float a00 = (float)s_a[k].x, a01 = (float)(0.5 * s_a[k].y), a11 = (float)s_b[k].x;
@@ -439,7 +564,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 // atomic touches a few 64-byte lines
                 for (int idx = tid; idx < nb * NG; idx += NT) {
                     const int k = idx / NG, f = idx - k * NG;
-                    const float sg = s_g[k][f];
+                    const float sg = s_g[0][k][f];
                     if (sg != 0.0f) unsafeAtomicAdd(&a.sgrad[(int64_t)s_rec[k] * 16 + f], sg);
                 }
                 __syncthreads();
@@ -492,38 +617,43 @@ __global__ __launch_bounds__(TW *TH) void raster_stats_kernel(RasterArgs a, int6
     }
 }
 
-// Wave-level work of the reverse pass, with its exact traversal (staging,
-// culling, per-wave lists): out[3] += list entries walked, out[4] += those
-// with at least one contributing lane.  One workgroup per tile.
+// Wavefront-level work of the reverse pass, with its exact traversal (staging,
+// block and quadrant lists): out[3] += wavefront steps (each step the four rows
+// take one entry of their lists), out[4] += steps with at least one pixel with
+// r^2 < 1.  One workgroup per tile.
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(TW *TH) void raster_wave_stats_kernel(RasterArgs a, int64_t *out)
 {
     using G = Geo<TW, TH>;
     __shared__ double2 s_c[BATCH], s_a[BATCH], s_b[BATCH];
     __shared__ float4 s_col[BATCH];
-    __shared__ uint8_t s_list[G::NW][BATCH];
+    __shared__ uint8_t s_blist[G::NW][BATCH];
+    __shared__ uint8_t s_rows[G::NW][4 * BATCH];
     __shared__ int32_t s_maxlast;
     const Staged S{s_c, s_a, s_b, s_col, nullptr};
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-    const int lx = (w % G::BX) * 8 + (lane & 7), ly = (w / G::BX) * 8 + (lane >> 3);
-    const double fpx = (double)lx + 0.5, fpy = (double)ly + 0.5;
+    const LanePixel<TW, TH> P(w, lane);
+    const double fpx = (double)P.lx + 0.5, fpy = (double)P.ly + 0.5;
+    const uint8_t *my_row = &s_rows[w][P.row * BATCH];
     const uint32_t g = blockIdx.x;
     const int v = find_view(a.views, a.n_views, g);
     const ViewDesc &V = a.views[v];
     const uint32_t lt = g - (uint32_t)V.tile_offset;
     const int ox = (int)(lt % (uint32_t)V.tiles_x) * TW, oy = (int)(lt / (uint32_t)V.tiles_x) * TH;
     const uint2 rg = a.ranges[g];
-    const int px = ox + lx, py = oy + ly;
+    const int px = ox + P.lx, py = oy + P.ly;
     int32_t last = -1;
     if (px < V.width && py < V.height) last = a.last_index[V.pixel_offset + (int64_t)py * V.width + px];
     if (last >= (int32_t)rg.y) last = (int32_t)rg.y - 1;
     if (tid == 0) s_maxlast = -1;
     __syncthreads();
     const int32_t wave_last = wave_max_i32(last);
+    int32_t row_last[4];
+    row_max4_i32(last, row_last);
     if (lane == 0 && wave_last >= 0) atomicMax(&s_maxlast, wave_last);
     __syncthreads();
     const int64_t maxlast = s_maxlast;
-    uint64_t walked = 0, active = 0;
+    uint64_t steps_n = 0, active = 0;
     for (int64_t hi = maxlast + 1; hi > (int64_t)rg.x; hi -= BATCH) {
         const int64_t lo = hi - BATCH > (int64_t)rg.x ? hi - BATCH : (int64_t)rg.x;
         const int nb = (int)(hi - lo);
@@ -531,29 +661,37 @@ __global__ __launch_bounds__(TW *TH) void raster_wave_stats_kernel(RasterArgs a,
         __syncthreads();
         const int64_t kmax64 = (int64_t)wave_last - lo;
         const int nbw = kmax64 < (int64_t)(nb - 1) ? (int)kmax64 + 1 : nb;
-        const int cnt = nbw > 0 ? build_list(s_col, nbw, w, s_list[w], lane) : 0;
-        for (int t = cnt - 1; t >= 0; --t) {
-            const int k = s_list[w][t];
+        const int cnt_b = nbw > 0 ? build_list(s_col, nbw, w, s_blist[w], lane) : 0;
+        int cnt[4];
+        build_rows<BATCH>(S, s_blist[w], cnt_b, P.bx, P.by, lo, row_last, s_rows[w], cnt, lane);
+        const int my_cnt = pick4(cnt, P.row), steps = max4(cnt);
+        for (int step = 0; step < steps; ++step) {
+            const int t = my_cnt - 1 - step;
+            const bool has = t >= 0;
+            const int k = has ? my_row[t] : 0;
             const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
             const double r2 = eval_r2(fpx - c.x, fpy - c.y, aa.x, aa.y, bb.x);
-            const bool contrib = (int32_t)(lo + k) <= last && r2 < 1.0;
-            walked += 1;
+            const bool contrib = has && (int32_t)(lo + k) <= last && r2 < 1.0;
+            steps_n += 1;
             active += __ballot(contrib) != 0;
         }
         __syncthreads();
     }
     if (lane == 0) {
-        atomicAdd((unsigned long long *)&out[3], (unsigned long long)walked);
+        atomicAdd((unsigned long long *)&out[3], (unsigned long long)steps_n);
         atomicAdd((unsigned long long *)&out[4], (unsigned long long)active);
     }
 }
 
 // ---------------------------------------------------------------- dispatch
 
+// The reverse pass keeps per-wavefront sums for every staged splat in LDS, so
+// it stages at most 128 splats at a time (256 would halve its occupancy).
 template <int TW, int TH, int BATCH>
 struct Kern {
+    static constexpr int BWD_BATCH = BATCH < 128 ? BATCH : 128;
     static void *fwd() { return (void *)raster_fwd_kernel<TW, TH, BATCH>; }
-    static void *bwd() { return (void *)raster_bwd_kernel<TW, TH, BATCH>; }
+    static void *bwd() { return (void *)raster_bwd_kernel<TW, TH, BWD_BATCH>; }
 };
 
 struct Entry {
@@ -682,8 +820,7 @@ hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t 
     if (tw == TW && th == TH) {                                                               \
         raster_stats_kernel<TW, TH><<<grid, block, 0, s>>>(a, out);                          \
         if (cfg.batch == 64) raster_wave_stats_kernel<TW, TH, 64><<<grid, block, 0, s>>>(a, out);   \
-        else if (cfg.batch == 128) raster_wave_stats_kernel<TW, TH, 128><<<grid, block, 0, s>>>(a, out); \
-        else raster_wave_stats_kernel<TW, TH, 256><<<grid, block, 0, s>>>(a, out);            \
+        else raster_wave_stats_kernel<TW, TH, 128><<<grid, block, 0, s>>>(a, out);            \
         return hipGetLastError();                                                             \
     }
     DBS_STATS(16, 16) DBS_STATS(16, 8) DBS_STATS(8, 8) DBS_STATS(32, 8) DBS_STATS(32, 16)

@@ -1,5 +1,7 @@
-// Sum of ten per-lane floats over a 64-lane wavefront (gfx950).
+// Cross-lane sums of ten per-lane floats (gfx950): over a whole 64-lane
+// wavefront (wave_reduce10), or over each 16-lane row (row_reduce10).
 //
+// wave_reduce10:
 // A multi-value butterfly: each exchange step halves the number of live
 // registers, so ten values cost 5 + 3 swaps and 12 row-local DPP adds instead
 // of 10 x 6 cross-lane shuffles.
@@ -57,5 +59,76 @@ __device__ __forceinline__ void wave_reduce10(const float v[10], float out[3])
 
 // Field held in out[0] by the lanes of 16-lane row `row` (out[1]: +4; out[2]: 8 + row/2 for even rows).
 __device__ __forceinline__ int reduce10_field0(int row) { return ((row & 1) << 1) | (row >> 1); }
+
+// row_reduce10: the same halving idea inside each 16-lane row, with DPP
+// exchanges only (no cross-row traffic).  At exchange distance 8 (row_ror:8),
+// 4 (row_half_mirror), 2 and 1 (quad_perm xor 2, xor 1) a pair of registers
+// (a, b) becomes one: lanes of the lower half of each exchanged pair keep
+// a + partner's a, lanes of the upper half b + partner's b.  Every exchange
+// pairs lanes that hold the same value with disjoint sets of summed lanes, so
+// after four exchanges each lane holds a full row total.  Ten values:
+// 5 + 2 + 1 + 1 halvings (3 VALU each) and 2 plain adds, 29 VALU in all.
+// On return lane l of a row holds the row total of value row10_field(l)
+// (-1: a duplicate, not to be stored); each value has exactly one owner.
+constexpr int kDppRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_partner(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float halve2(float a, float b, bool upper)
+{
+    const float send = upper ? a : b;
+    const float keep = upper ? b : a;
+    return keep + dpp_partner<CTRL>(send);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float fold1(float a) { return a + dpp_partner<CTRL>(a); }
+
+__device__ __forceinline__ float row_reduce10(const float v[10], int lane)
+{
+    const bool u8 = lane & 8, u4 = lane & 4, u2 = lane & 2, u1 = lane & 1;
+    const float a0 = halve2<kDppRor8>(v[0], v[1], u8);
+    const float a1 = halve2<kDppRor8>(v[2], v[3], u8);
+    const float a2 = halve2<kDppRor8>(v[4], v[5], u8);
+    const float a3 = halve2<kDppRor8>(v[6], v[7], u8);
+    const float a4 = halve2<kDppRor8>(v[8], v[9], u8);
+    const float b0 = halve2<kDppHalfMirror>(a0, a1, u4);
+    const float b1 = halve2<kDppHalfMirror>(a2, a3, u4);
+    const float b2 = fold1<kDppHalfMirror>(a4);
+    const float c0 = halve2<kDppXor2>(b0, b1, u2);
+    const float c1 = fold1<kDppXor2>(b2);
+    return halve2<kDppXor1>(c0, c1, u1);
+}
+
+// Owner table of row_reduce10 (value held by lane l of a row, -1: duplicate).
+__device__ __forceinline__ int row10_field(int lane)
+{
+    // lanes 0..15: 0, 8, 4, -, 2, -, 6, -, 1, 9, 5, -, 3, -, 7, -  (4 bits each, 15 = -)
+    constexpr uint64_t kPacked = 0xf7f3f591f6f2f480ull;
+    const int f = (int)((kPacked >> (4 * (lane & 15))) & 15u);
+    return f == 15 ? -1 : f;
+}
+
+// Value of x held by the same lane position in row r^1 / r^2 (v_permlane16_swap
+// exchanges odd rows of its first operand with even rows of its second,
+// v_permlane32_swap the upper half of the first with the lower of the second).
+__device__ __forceinline__ float from_row_xor1(float x, int row)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, x),
+                                                   false, false);
+    return __builtin_bit_cast(float, (unsigned)((row & 1) ? r[0] : r[1]));
+}
+
+__device__ __forceinline__ float from_row_xor2(float x, int row)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, x),
+                                                   false, false);
+    return __builtin_bit_cast(float, (unsigned)((row & 2) ? r[0] : r[1]));
+}
 
 }  // namespace dbs

@@ -176,7 +176,7 @@ class Rasterizer:
             C.c_void_p(out.data_ptr()), _stream()))
         o = out.cpu().tolist()
         return {"bwd_evaluated": o[0], "contributing": o[1], "fwd_evaluated": o[2],
-                "bwd_wave_entries": o[3], "bwd_wave_entries_active": o[4]}
+                "bwd_wave_steps": o[3], "bwd_wave_steps_active": o[4]}
 
     # ---- eager helpers ----
     def forward(self, params: dict, outputs=None):
