@@ -46,6 +46,30 @@ def step_bytes(q_floats: int, n: int, visible: int, pairs: int, pixels: int) -> 
     return 12 * q_floats * n + 128 * visible + 124 * pairs + 40 * pixels
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_counters_config3.txt")
+TRAFFIC_SOURCES = ("paper_2501_18630_amd/csrc/raster.hip", "paper_2501_18630_amd/csrc/wave_reduce.h",
+                   "paper_2501_18630_amd/csrc/dbs_internal.h")
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the raster reverse pass from the committed
+    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when the summary
+    is for another workload or the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_FILE).read().splitlines()
+                      if line.startswith("traffic_"))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("traffic_sources_sha256") != h.hexdigest() or fields.get("traffic_workload") != workload:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -236,7 +260,8 @@ def main():
         "batched_speedup": round(mpix / per_view, 3) if per_view else None,
         "roofline": {"kernel": "raster_bwd_kernel", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": measured_traffic(f"config {args.config}, tile {tw}x{th}, batch {cfg.batch}"),
                      "flops_per_launch": bwd_flops, "ms_per_launch": round(st["raster_bwd"], 4)},
         "step_hbm": {"algorithmic_bytes": sb, "achieved_GBs": round(sb / t_batched / 1e9, 1),
                      "peak_GBs": HBM_PEAK_GBS, "frac": round(sb / t_batched / 1e9 / HBM_PEAK_GBS, 4)},
