@@ -64,11 +64,17 @@ __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp,
     double dS[6] = {0, 0, 0, 0, 0, 0};  // adjoint of Sigma (full-matrix entries xx xy xz yy yz zz)
     bool any = false;
 
+    // Lines of records the raster pass never touched (culled, or no pixel
+    // reached) are zero.  Each view's line is loaded one view ahead so that
+    // its latency overlaps the previous view's arithmetic.
+    float4 na = P.sgrad[4 * i], nb = P.sgrad[4 * i + 1];
     for (int32_t v = 0; v < n_views; ++v) {
-        const int64_t rec = (int64_t)v * n + i;
-        if (P.ntiles[rec] == 0) continue;
-        const float4 *line = P.sgrad + 4 * rec;
-        const float4 ga = line[0], gbv = line[1];
+        const float4 ga = na, gbv = nb;
+        if (v + 1 < n_views) {
+            const float4 *nl = P.sgrad + 4 * ((int64_t)(v + 1) * n + i);
+            na = nl[0];
+            nb = nl[1];
+        }
         // ga = (dmu'x, dmu'y, G00, G01), gbv = (G11, do, db, -)
         if (ga.x == 0.f && ga.y == 0.f && ga.z == 0.f && ga.w == 0.f && gbv.x == 0.f && gbv.y == 0.f &&
             gbv.z == 0.f)
@@ -209,11 +215,17 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
         gcm[m][0] = gcm[m][1] = gcm[m][2] = 0.0f;
     }
     bool any = false;
+    // one view ahead, as in the geometry kernel
+    float4 na = P.sgrad[4 * i], nb = P.sgrad[4 * i + 1], nc = P.sgrad[4 * i + 2];
     for (int32_t v = 0; v < n_views; ++v) {
-        const int64_t rec = (int64_t)v * n + i;
-        if (P.ntiles[rec] == 0) continue;
-        float4 *line = P.sgrad + 4 * rec;
-        const float4 ga = line[0], gbv = line[1], gcv = line[2];
+        float4 *line = P.sgrad + 4 * ((int64_t)v * n + i);
+        const float4 ga = na, gbv = nb, gcv = nc;
+        if (v + 1 < n_views) {
+            const float4 *nl = line + 4 * n;
+            na = nl[0];
+            nb = nl[1];
+            nc = nl[2];
+        }
         if (line_is_zero(ga, gbv, gcv)) continue;
         {
             const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -15,8 +15,9 @@
 //
 // The radix sort is a classic LSD sort with 8-bit digits: per-block digit
 // histograms (upsweep), a device-wide exclusive scan of the digit-major
-// histogram, and a stable scatter (downsweep) that ranks each block's keys in
-// LDS with wave ballots and writes them out digit-contiguous.  Element counts
+// histogram, and a stable scatter (downsweep) that ranks each block's keys
+// with wave ballots and per-wave digit counts in LDS (no LDS atomics, one
+// barrier per phase) and writes them out digit-contiguous.  Element counts
 // are read from device memory, so the whole pipeline runs without a host
 // round trip and can be captured in a graph.
 #include "dbs_internal.h"
@@ -205,30 +206,49 @@ __device__ inline uint64_t match_digit(uint32_t d, bool valid)
     return peers;
 }
 
+// Block b sorts elements [b * kSortTile, (b + 1) * kSortTile); inside it wave w
+// owns the contiguous 1024 elements from w * 1024, item k of lane l being
+// element w * 1024 + k * 64 + l, so that (wave, item, lane) is element order.
+// Digit counts are kept per wavefront in LDS and updated by one leader lane
+// per distinct digit with a plain read-add-write: the leaders of one wave
+// hold distinct digits, and no other wave touches the wave's row.  (LDS
+// float/int atomics serialise lanes; these updates are conflict-free.)
+__device__ __forceinline__ int64_t sort_elem(int64_t block_base, int w, int k, int lane)
+{
+    return block_base + (int64_t)w * (kSortItems * kWave) + (int64_t)k * kWave + lane;
+}
+
 __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint32_t *keys, Count cnt,
                                                                      int shift, uint32_t *hist, int64_t nblocks)
 {
-    __shared__ uint32_t s_cnt[kRadix];
+    constexpr int NW = kSortThreads / kWave;
+    __shared__ uint32_t s_cnt[NW][kRadix];
+    const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
     const int64_t n = cnt.get();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    s_cnt[threadIdx.x] = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) s_cnt[ww][t] = 0;
     __syncthreads();
     if (base < n) {
         uint32_t d[kSortItems];
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before any ranking
-            const int64_t e = base + (int64_t)k * kSortThreads + threadIdx.x;
+        for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before any counting
+            const int64_t e = sort_elem(base, w, k, lane);
             d[k] = e < n ? (keys[e] >> shift) & (kRadix - 1) : kRadix;
         }
+        const uint64_t lt = lanemask_lt();
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
             const bool valid = d[k] < kRadix;
             const uint64_t peers = match_digit(d[k], valid);
-            if (valid && (peers & lanemask_lt()) == 0) atomicAdd(&s_cnt[d[k]], (uint32_t)__popcll(peers));
+            if (valid && (peers & lt) == 0) s_cnt[w][d[k]] += (uint32_t)__popcll(peers);
         }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_cnt[threadIdx.x];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) tot += s_cnt[ww][t];
+    hist[(int64_t)t * nblocks + blockIdx.x] = tot;
 }
 
 // If gather_src is set, also writes gather_out[o] = gather_src[value] at each
@@ -238,68 +258,58 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     uint32_t *__restrict__ vals_out, Count cnt, int shift, const uint32_t *hist, int64_t nblocks,
     const uint2 *__restrict__ gather_src, uint2 *__restrict__ gather_out)
 {
+    constexpr int NW = kSortThreads / kWave;
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
-    __shared__ uint32_t s_wcnt[2][kSortThreads / kWave][kRadix];
-    __shared__ uint32_t s_run[kRadix];
+    __shared__ uint32_t s_wh[NW][kRadix];   // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t s_start[kRadix];
     __shared__ uint32_t s_goff[kRadix];
-    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
+    __shared__ uint32_t s_tmp[NW + 1];
 
     const int64_t n = cnt.get();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     if (base >= n) return;  // uniform across the block
-    const int t = threadIdx.x, w = t / kWave;
-    s_run[t] = 0;
+    const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
     s_goff[t] = hist[(int64_t)t * nblocks + blockIdx.x];
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int ww = 0; ww < kSortThreads / kWave; ++ww) s_wcnt[b][ww][t] = 0;
+    for (int ww = 0; ww < NW; ++ww) s_wh[ww][t] = 0;
     __syncthreads();
 
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking rounds
-        const int64_t e = base + (int64_t)k * kSortThreads + t;
+    for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
+        const int64_t e = sort_elem(base, w, k, lane);
         key[k] = e < n ? keys_in[e] : 0u;
         val[k] = e < n ? vals_in[e] : 0u;
     }
+    // rank inside the wave: earlier items of this wave, then lower lanes of this item
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
-        const int64_t e = base + (int64_t)k * kSortThreads + t;
-        const bool valid = e < n;
+        const bool valid = sort_elem(base, w, k, lane) < n;
         const uint32_t d = (key[k] >> shift) & (kRadix - 1);
         const uint64_t peers = match_digit(d, valid);
-        const uint32_t in_wave = (uint32_t)__popcll(peers & lt);
-        const int buf = k & 1;
-        if (valid && in_wave == 0) s_wcnt[buf][w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        {   // thread t owns digit t: prefix over the waves of this round
-            uint32_t r = s_run[t];
-#pragma unroll
-            for (int ww = 0; ww < kSortThreads / kWave; ++ww) {
-                const uint32_t c = s_wcnt[buf][ww][t];
-                s_wcnt[buf][ww][t] = r;
-                r += c;
-            }
-            s_run[t] = r;
-#pragma unroll
-            for (int ww = 0; ww < kSortThreads / kWave; ++ww) s_wcnt[buf ^ 1][ww][t] = 0;
-        }
-        __syncthreads();
-        rank[k] = s_wcnt[buf][w][d] + in_wave;
+        const uint32_t before = s_wh[w][d];
+        if (valid && (peers & lt) == 0) s_wh[w][d] = before + (uint32_t)__popcll(peers);
+        rank[k] = before + (uint32_t)__popcll(peers & lt);
     }
-    uint32_t start = block_exclusive_scan(s_run[t], s_tmp, nullptr);
-    s_start[t] = start;
+    __syncthreads();
+    {   // thread t owns digit t: offsets of the waves, then of the digits
+        uint32_t run = 0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            const uint32_t c = s_wh[ww][t];
+            s_wh[ww][t] = run;
+            run += c;
+        }
+        s_start[t] = block_exclusive_scan(run, s_tmp, nullptr);
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
-        const int64_t e = base + (int64_t)k * kSortThreads + t;
-        if (e < n) {
+        if (sort_elem(base, w, k, lane) < n) {
             const uint32_t d = (key[k] >> shift) & (kRadix - 1);
-            const uint32_t pos = s_start[d] + rank[k];
+            const uint32_t pos = s_start[d] + s_wh[w][d] + rank[k];
             s_keys[pos] = key[k];
             s_vals[pos] = val[k];
         }
