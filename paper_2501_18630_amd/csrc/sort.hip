@@ -213,6 +213,19 @@ __device__ inline uint64_t match_digit(uint32_t d, bool valid)
 // per distinct digit with a plain read-add-write: the leaders of one wave
 // hold distinct digits, and no other wave touches the wave's row.  (LDS
 // float/int atomics serialise lanes; these updates are conflict-free.)
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD
+// b % 8) and every XCD has its own L2.  Chunk c of the keys is given to
+// workgroup b with c = (b % 8) * (nb / 8) + b / 8 (up to the last nb % 8), so
+// that each XCD sorts a contiguous range of chunks: the digit-major histogram
+// entries a workgroup writes, and the boundaries of the digit runs it
+// scatters, then share cache lines with its neighbours on the same XCD
+// instead of being written back piecewise by several L2s.
+__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nb)
+{
+    const int64_t full = nb & ~(int64_t)7;
+    return b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
+}
+
 __device__ __forceinline__ int64_t sort_elem(int64_t block_base, int w, int k, int lane)
 {
     return block_base + (int64_t)w * (kSortItems * kWave) + (int64_t)k * kWave + lane;
@@ -225,7 +238,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
     __shared__ uint32_t s_cnt[NW][kRadix];
     const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
     const int64_t n = cnt.get();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t nb_used = (n + kSortTile - 1) / kSortTile;  // the grid is sized for the capacity
+    const int64_t chunk = (int64_t)blockIdx.x < nb_used ? xcd_chunk(blockIdx.x, nb_used) : (int64_t)blockIdx.x;
+    const int64_t base = chunk * kSortTile;
 #pragma unroll
     for (int ww = 0; ww < NW; ++ww) s_cnt[ww][t] = 0;
     __syncthreads();
@@ -248,7 +263,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
     uint32_t tot = 0;
 #pragma unroll
     for (int ww = 0; ww < NW; ++ww) tot += s_cnt[ww][t];
-    hist[(int64_t)t * nblocks + blockIdx.x] = tot;
+    hist[(int64_t)t * nblocks + chunk] = tot;
 }
 
 // If gather_src is set, also writes gather_out[o] = gather_src[value] at each
@@ -267,10 +282,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     __shared__ uint32_t s_tmp[NW + 1];
 
     const int64_t n = cnt.get();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t nb_used = (n + kSortTile - 1) / kSortTile;  // the grid is sized for the capacity
+    const int64_t chunk = (int64_t)blockIdx.x < nb_used ? xcd_chunk(blockIdx.x, nb_used) : (int64_t)blockIdx.x;
+    const int64_t base = chunk * kSortTile;
     if (base >= n) return;  // uniform across the block
     const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
-    s_goff[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+    s_goff[t] = hist[(int64_t)t * nblocks + chunk];
 #pragma unroll
     for (int ww = 0; ww < NW; ++ww) s_wh[ww][t] = 0;
     __syncthreads();
