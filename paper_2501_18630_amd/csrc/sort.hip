@@ -416,7 +416,8 @@ struct StoreCompact {
 
 // One block per 256 depth-ordered records: the block's pairs are generated
 // cooperatively, thread p writing pair p of the block (found by binary search
-// over the records' pair offsets), so that every store is contiguous.
+// over the records' pair offsets), so that every store is contiguous.  (An
+// XCD-ordered chunk assignment, as in the radix passes, measured slower here.)
 __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, const uint32_t *sorted_rec,
                                                          const uint32_t *pair_off, const short4 *sorted_box,
                                                          const ViewDesc *views, uint32_t n, int tw, int th,
@@ -465,15 +466,35 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t count, uint32_t value)
     if (i < count) p[i] = value;
 }
 
+// Tile ranges from the sorted keys: 4096 keys per workgroup staged in LDS
+// with one neighbour on each side; a range starts (ends) where a key differs
+// from its predecessor (successor).
 __global__ __launch_bounds__(256) void tile_ranges_kernel(const BinsHeader *bh, const uint32_t *skeys,
                                                           uint2 *ranges)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint32_t s_k[4096 + 2];
     const int64_t K = bh->n_pairs;
-    if (j >= K) return;
-    const uint32_t k = skeys[j];
-    if (j == 0 || skeys[j - 1] != k) ranges[k].x = (uint32_t)j;
-    if (j == K - 1 || skeys[j + 1] != k) ranges[k].y = (uint32_t)(j + 1);
+    const int64_t base = (int64_t)blockIdx.x * 4096;
+    if (base >= K) return;  // uniform
+    const int t = threadIdx.x;
+    const int cnt = K - base < 4096 ? (int)(K - base) : 4096;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int e = k * 256 + t;
+        s_k[1 + e] = e < cnt ? skeys[base + e] : 0xffffffffu;
+    }
+    if (t == 0) s_k[0] = base > 0 ? skeys[base - 1] : 0xffffffffu;
+    if (t == 1) s_k[1 + cnt] = base + cnt < K ? skeys[base + cnt] : 0xffffffffu;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int e = k * 256 + t;
+        if (e < cnt) {
+            const uint32_t key = s_k[1 + e];
+            if (s_k[e] != key) ranges[key].x = (uint32_t)(base + e);
+            if (s_k[2 + e] != key) ranges[key].y = (uint32_t)(base + e + 1);
+        }
+    }
 }
 
 // Heaviest tiles first: key = 0xffff - min(pairs, 0xffff).
@@ -551,7 +572,7 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
         const uint32_t *skeys = pairs_in_b ? pkeys_b : pkeys_a;
         fill_u32_kernel<<<(unsigned)ceil_div(2 * n_tiles, 256), 256, 0, s>>>((uint32_t *)B.tile_range,
                                                                              2 * n_tiles, 0u);
-        tile_ranges_kernel<<<(unsigned)ceil_div(cap, 256), 256, 0, s>>>(B.hdr, skeys, B.tile_range);
+        tile_ranges_kernel<<<(unsigned)ceil_div(cap, 4096), 256, 0, s>>>(B.hdr, skeys, B.tile_range);
     } else {
         fill_u32_kernel<<<(unsigned)ceil_div(2 * n_tiles, 256), 256, 0, s>>>((uint32_t *)B.tile_range,
                                                                              2 * n_tiles, 0u);
