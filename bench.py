@@ -199,7 +199,9 @@ def main():
     step = renderer.TrainStep(rast, params, target_flat, headroom=1.1, use_graph=True)
     for _ in range(args.warmup):
         step.run()
+    torch.cuda.reset_peak_memory_stats()
     t_batched = timed(step.run, args.steps)
+    peak_mem = torch.cuda.max_memory_allocated()
     assert not step.overflowed()
     log(f"batched: {t_batched * 1e3:.3f} ms/step")
 
@@ -256,6 +258,7 @@ def main():
                                f"{m} lobes, tile {tw}x{th}, batch {cfg.batch}"
                                f"{' (autotuned)' if args.tile == 'auto' else ''}, batched + hipGraph",
                    "views": len(cams), "pixels": X, "splats": n, "lobes": m},
+        "peak_device_memory_GiB": round(peak_mem / 2**30, 2),
         "per_view_value": round(per_view, 3) if per_view else None,
         "batched_speedup": round(mpix / per_view, 3) if per_view else None,
         "roofline": {"kernel": "raster_bwd_kernel", "bound": "alu", "achieved": round(achieved, 3),

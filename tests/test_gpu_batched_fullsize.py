@@ -1,6 +1,6 @@
 """Batched path at the benchmark's sizes and launch configuration: graph
-replay equals eager, sampled pixels and tiles of configs 2 and 3 against the
-oracle, a crop-restricted gradient at full scene size.  Needs an MI355X."""
+replay equals eager, sampled pixels and tiles of configs 2, 3 and 4 against
+the oracle, a crop-restricted gradient at full scene size.  Needs an MI355X."""
 import numpy as np
 import pytest
 
@@ -126,3 +126,21 @@ def test_fullsize_crop_gradient_batched(oracle, config3):
     far = np.setdiff1d(np.arange(s["means"].shape[0]), near)
     for k in PARAMS:
         assert not np.any(out["grads"][k][far]), k
+
+
+def test_config4_sampled_pixels(oracle):
+    """32 mixed-resolution views over 6M splats, batched: sampled pixels of
+    three views against the oracle (and the device memory the step holds)."""
+    import torch
+    from gpu_helpers import gpu_render
+    s, cams = scenes.config4()
+    torch.cuda.reset_peak_memory_stats()
+    out = gpu_render(s, cams)
+    print(f"config 4: peak device memory {torch.cuda.max_memory_allocated() / 2**30:.1f} GiB")
+    rng = np.random.default_rng(14)
+    for v in (0, 16, 31):
+        cam = cams[v]
+        pix = _pixels(rng, cam["width"], cam["height"], 32)
+        ref = oracle.render(s, cam, float(AMAX), float(TEPS), pixels=pix)
+        gpu = out["images"][v][:, pix[:, 1], pix[:, 0]].T
+        assert_image_close(gpu, ref["rgb"], ref["T"], ref["T_prev"])
