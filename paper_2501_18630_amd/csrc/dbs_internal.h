@@ -98,8 +98,8 @@ inline BinsLayout bins_layout(int64_t cap, int64_t n_tiles) {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // elements per block
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
+constexpr int kMaxRadixBits = 9;  // digits of 8 or 9 bits
+constexpr int kMaxRadix = 1 << kMaxRadixBits;
 constexpr int kScanTile = 4096;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -118,7 +118,7 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     if (cap > maxn) maxn = cap;
     if (n_tiles > maxn) maxn = n_tiles;
     L.hist_blocks = ceil_div(maxn > 0 ? maxn : 1, kSortTile);
-    size_t hist_n = (size_t)L.hist_blocks * kRadix;
+    size_t hist_n = (size_t)L.hist_blocks * kMaxRadix;
     size_t part_n = (size_t)ceil_div((int64_t)(hist_n > R + 1 ? hist_n : R + 1), kScanTile) + 64;
     L.keys_a = o;   o = align_up(o + 4 * R);
     L.vals_a = o;   o = align_up(o + 4 * R);

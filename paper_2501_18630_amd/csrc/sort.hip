@@ -193,12 +193,13 @@ struct StoreArray {
 
 // ---------------------------------------------------------------- radix sort
 
-// 8-bit digit match across the wave: mask of valid lanes holding digit d.
+// Digit match across the wave: mask of valid lanes holding digit d (RB bits).
+template <int RB>
 __device__ inline uint64_t match_digit(uint32_t d, bool valid)
 {
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < RB; ++b) {
         const bool bit = (d >> b) & 1u;
         const uint64_t bal = __ballot(bit);
         peers &= bit ? bal : ~bal;
@@ -231,55 +232,65 @@ __device__ __forceinline__ int64_t sort_elem(int64_t block_base, int w, int k, i
     return block_base + (int64_t)w * (kSortItems * kWave) + (int64_t)k * kWave + lane;
 }
 
-__global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint32_t *keys, Count cnt,
-                                                                     int shift, uint32_t *hist, int64_t nblocks)
+template <int RB>
+__global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint32_t *keys, Count cnt, int shift,
+                                                                     int width, uint32_t *hist, int64_t nblocks)
 {
-    constexpr int NW = kSortThreads / kWave;
-    __shared__ uint32_t s_cnt[NW][kRadix];
+    constexpr int NW = kSortThreads / kWave, RADIX = 1 << RB, DPT = RADIX / kSortThreads;
+    __shared__ uint32_t s_cnt[NW][RADIX];
+    const uint32_t dmask = (1u << width) - 1u;
     const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
     const int64_t n = cnt.get();
     const int64_t nb_used = (n + kSortTile - 1) / kSortTile;  // the grid is sized for the capacity
     const int64_t chunk = (int64_t)blockIdx.x < nb_used ? xcd_chunk(blockIdx.x, nb_used) : (int64_t)blockIdx.x;
     const int64_t base = chunk * kSortTile;
 #pragma unroll
-    for (int ww = 0; ww < NW; ++ww) s_cnt[ww][t] = 0;
+    for (int ww = 0; ww < NW; ++ww)
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) s_cnt[ww][q * kSortThreads + t] = 0;
     __syncthreads();
     if (base < n) {
         uint32_t d[kSortItems];
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before any counting
             const int64_t e = sort_elem(base, w, k, lane);
-            d[k] = e < n ? (keys[e] >> shift) & (kRadix - 1) : kRadix;
+            d[k] = e < n ? (keys[e] >> shift) & dmask : RADIX;
         }
         const uint64_t lt = lanemask_lt();
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            const bool valid = d[k] < kRadix;
-            const uint64_t peers = match_digit(d[k], valid);
+            const bool valid = d[k] < RADIX;
+            const uint64_t peers = match_digit<RB>(d[k], valid);
             if (valid && (peers & lt) == 0) s_cnt[w][d[k]] += (uint32_t)__popcll(peers);
         }
     }
     __syncthreads();
-    uint32_t tot = 0;
 #pragma unroll
-    for (int ww = 0; ww < NW; ++ww) tot += s_cnt[ww][t];
-    hist[(int64_t)t * nblocks + chunk] = tot;
+    for (int q = 0; q < DPT; ++q) {
+        const int dd = q * kSortThreads + t;
+        uint32_t tot = 0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) tot += s_cnt[ww][dd];
+        hist[(int64_t)dd * nblocks + chunk] = tot;
+    }
 }
 
 // If gather_src is set, also writes gather_out[o] = gather_src[value] at each
 // output position o (used to carry a per-value field through the last pass).
+template <int RB>
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
-    uint32_t *__restrict__ vals_out, Count cnt, int shift, const uint32_t *hist, int64_t nblocks,
+    uint32_t *__restrict__ vals_out, Count cnt, int shift, int width, const uint32_t *hist, int64_t nblocks,
     const uint2 *__restrict__ gather_src, uint2 *__restrict__ gather_out)
 {
-    constexpr int NW = kSortThreads / kWave;
+    constexpr int NW = kSortThreads / kWave, RADIX = 1 << RB, DPT = RADIX / kSortThreads;
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
-    __shared__ uint32_t s_wh[NW][kRadix];   // per-wave digit counts, then per-wave offsets
-    __shared__ uint32_t s_start[kRadix];
-    __shared__ uint32_t s_goff[kRadix];
+    __shared__ uint32_t s_wh[NW][RADIX];   // per-wave digit counts, then per-wave offsets
+    __shared__ uint32_t s_start[RADIX];
+    __shared__ uint32_t s_goff[RADIX];
     __shared__ uint32_t s_tmp[NW + 1];
+    const uint32_t dmask = (1u << width) - 1u;
 
     const int64_t n = cnt.get();
     const int64_t nb_used = (n + kSortTile - 1) / kSortTile;  // the grid is sized for the capacity
@@ -287,9 +298,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const int64_t base = chunk * kSortTile;
     if (base >= n) return;  // uniform across the block
     const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
-    s_goff[t] = hist[(int64_t)t * nblocks + chunk];
 #pragma unroll
-    for (int ww = 0; ww < NW; ++ww) s_wh[ww][t] = 0;
+    for (int q = 0; q < DPT; ++q) {
+        const int dd = q * kSortThreads + t;
+        s_goff[dd] = hist[(int64_t)dd * nblocks + chunk];
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) s_wh[ww][dd] = 0;
+    }
     __syncthreads();
 
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
@@ -304,28 +319,40 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const bool valid = sort_elem(base, w, k, lane) < n;
-        const uint32_t d = (key[k] >> shift) & (kRadix - 1);
-        const uint64_t peers = match_digit(d, valid);
+        const uint32_t d = (key[k] >> shift) & dmask;
+        const uint64_t peers = match_digit<RB>(d, valid);
         const uint32_t before = s_wh[w][d];
         if (valid && (peers & lt) == 0) s_wh[w][d] = before + (uint32_t)__popcll(peers);
         rank[k] = before + (uint32_t)__popcll(peers & lt);
     }
     __syncthreads();
-    {   // thread t owns digit t: offsets of the waves, then of the digits
-        uint32_t run = 0;
+    {   // thread t owns digits t * DPT .. t * DPT + DPT - 1: offsets of the waves, then of the digits
+        uint32_t tot[DPT], sum = 0;
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) {
-            const uint32_t c = s_wh[ww][t];
-            s_wh[ww][t] = run;
-            run += c;
+        for (int q = 0; q < DPT; ++q) {
+            const int dd = t * DPT + q;
+            uint32_t run = 0;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint32_t c = s_wh[ww][dd];
+                s_wh[ww][dd] = run;
+                run += c;
+            }
+            tot[q] = run;
+            sum += run;
         }
-        s_start[t] = block_exclusive_scan(run, s_tmp, nullptr);
+        uint32_t st = block_exclusive_scan(sum, s_tmp, nullptr);
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) {
+            s_start[t * DPT + q] = st;
+            st += tot[q];
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         if (sort_elem(base, w, k, lane) < n) {
-            const uint32_t d = (key[k] >> shift) & (kRadix - 1);
+            const uint32_t d = (key[k] >> shift) & dmask;
             const uint32_t pos = s_start[d] + s_wh[w][d] + rank[k];
             s_keys[pos] = key[k];
             s_vals[pos] = val[k];
@@ -335,7 +362,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const int64_t cnt_blk = n - base < kSortTile ? n - base : kSortTile;
     for (int j = t; j < cnt_blk; j += kSortThreads) {
         const uint32_t kk = s_keys[j];
-        const uint32_t d = (kk >> shift) & (kRadix - 1);
+        const uint32_t d = (kk >> shift) & dmask;
         const uint32_t o = s_goff[d] + (uint32_t)j - s_start[d];
         const uint32_t vv = s_vals[j];
         keys_out[o] = kk;
@@ -344,32 +371,47 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     }
 }
 
+int radix_passes(int bits) { return (bits + kMaxRadixBits - 1) / kMaxRadixBits; }
+
 // Stable sort of (keys, vals) by key bits [bit_lo, bit_hi); ping-pongs
-// between the a and b buffers and reports where the result ended up.
+// between the a and b buffers and reports where the result ended up.  The
+// bits are split into radix_passes() digits of at most kMaxRadixBits, as
+// even as possible (17 bits: 9 + 8, not 8 + 8 + 1).
 hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Count cnt, int bit_lo,
                       int bit_hi, uint32_t *hist, uint32_t *partials, hipStream_t s, bool *result_in_b,
                       const uint2 *gather_src = nullptr, uint2 *gather_out = nullptr)
 {
     const int64_t nblocks = ceil_div(cnt.host > 0 ? cnt.host : 1, kSortTile);
+    const int bits = bit_hi - bit_lo, passes = radix_passes(bits);
     bool in_b = false;
-    for (int shift = bit_lo; shift < bit_hi; shift += kRadixBits) {
+    int shift = bit_lo;
+    for (int p = 0; p < passes; ++p) {
+        const int width = (bits - (shift - bit_lo) + (passes - p) - 1) / (passes - p);
         const uint32_t *kin = in_b ? kb : ka, *vin = in_b ? vb : va;
         uint32_t *kout = in_b ? ka : kb, *vout = in_b ? va : vb;
-        radix_upsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, hist, nblocks);
-        hipError_t e = device_scan(LoadArray{hist}, StoreArray{hist}, Count{nullptr, nblocks * kRadix},
-                                   partials, s);
+        const bool final_pass = p == passes - 1;
+        const int64_t nh = nblocks * ((int64_t)1 << width);
+        if (width <= 8)
+            radix_upsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, nblocks);
+        else
+            radix_upsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, nblocks);
+        hipError_t e = device_scan(LoadArray{hist}, StoreArray{hist}, Count{nullptr, nh}, partials, s);
         if (e != hipSuccess) return e;
-        const bool final_pass = shift + kRadixBits >= bit_hi;
-        radix_downsweep_kernel<<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-            kin, vin, kout, vout, cnt, shift, hist, nblocks, final_pass ? gather_src : nullptr,
-            final_pass ? gather_out : nullptr);
+        const uint2 *gs = final_pass ? gather_src : nullptr;
+        uint2 *go = final_pass ? gather_out : nullptr;
+        if (width <= 8)
+            radix_downsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, cnt, shift,
+                                                                                width, hist, nblocks, gs, go);
+        else
+            radix_downsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, cnt, shift,
+                                                                                width, hist, nblocks, gs, go);
         in_b = !in_b;
+        shift += width;
     }
     *result_in_b = in_b;
     return hipGetLastError();
 }
 
-int radix_passes(int bits) { return (bits + kRadixBits - 1) / kRadixBits; }
 
 // ---------------------------------------------------------------- binning kernels
 
