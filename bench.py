@@ -129,6 +129,25 @@ def stage_times(rast, step, steps):
     return {k: v / steps for k, v in acc.items()}
 
 
+def composite_loss_times(rast, step, steps, lam_ssim=0.2, lam_reg=0.01):
+    """Average ms of the composite-loss kernels of Sec. 3.4 on the step's
+    rendered images (the benchmark step itself uses L1): the photometric term
+    with SSIM, and the regularisers."""
+    import torch
+    t_p = t_r = 0.0
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        rast.photometric_loss(step.image, step.target, lam_ssim, step.dL, step.loss)
+        ev[1].record()
+        rast.regularizer(step.params, lam_reg, lam_reg, step.grads, step.loss)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_p += ev[0].elapsed_time(ev[1])
+        t_r += ev[1].elapsed_time(ev[2])
+    return t_p / steps, t_r / steps
+
+
 def work_counts(rast, step):
     """Pair counts and evaluated / contributing (pixel, pair) counts of the
     last step, from the library's counting pass (outside the timed region)."""
@@ -231,6 +250,8 @@ def main():
     log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
     wc = work_counts(rast, step)
     log(f"work: {wc}")
+    t_photo, t_reg = composite_loss_times(rast, step, max(3, args.steps // 2))
+    log(f"composite loss (ms): photometric {t_photo:.3f}, regularisers {t_reg:.3f}")
 
     mpix = X / t_batched / 1e6
     q_floats = 15 + 6 * m
@@ -270,6 +291,9 @@ def main():
                      "peak_GBs": HBM_PEAK_GBS, "frac": round(sb / t_batched / 1e9 / HBM_PEAK_GBS, 4)},
         "raster_fwd_tflops": round(fwd_flops / (st["raster_fwd"] * 1e-3) / 1e12, 3),
         "stage_ms": {k: round(v, 4) for k, v in st.items()},
+        # not in the step: the composite loss of the paper's training (lambda_SSIM = 0.2)
+        "composite_loss": {"photometric_ms": round(t_photo, 4), "regularizer_ms": round(t_reg, 4),
+                           "photometric_GBs": round(12 * 3 * X / (t_photo * 1e-3) / 1e9, 1)},
         "work": wc,
     }
     if not args.no_cpu_baseline:

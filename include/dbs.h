@@ -225,6 +225,32 @@ dbs_status dbs_render_stats(const void *projected, const void *bins, const dbs_c
 dbs_status dbs_l1_loss(const float *image, const float *target, int64_t count, float scale,
                        float *dL_dimage, float *loss, void *stream);
 
+/* ---- training loss (Sec. 3.4, composite loss equation) ------------------ */
+
+/* Photometric term of the composite loss, summed over the views of a batch:
+ *   L = sum_v [ (1 - lambda) mean|x - y| + lambda (1 - mean SSIM(x, y)) ],
+ * means over the 3 H_v W_v channel-pixels of view v.  SSIM per colour channel
+ * over an 11x11 Gaussian window (sigma 1.5) with zero padding outside the
+ * image, C1 = 0.01^2, C2 = 0.03^2 (the standard constants for [0, 1] images;
+ * the paper names SSIM without them).  image, target: [3 sum H W] floats in
+ * the dbs_render_fwd layout.  dL_dimage (same layout) is OVERWRITTEN with
+ * dL/dimage; loss (device float, may be NULL) is OVERWRITTEN with L.
+ * lambda_ssim in [0, 1] (the paper trains with 0.2).  cams: [host], only the
+ * sizes are read.  Allocates nothing; one work item per (view, channel,
+ * 32x16 tile). */
+dbs_status dbs_photometric_loss(const float *image, const float *target, const dbs_camera *cams /*[host]*/,
+                                int32_t n_views, float lambda_ssim, float *dL_dimage, float *loss, void *stream);
+
+/* Regularisers of the composite loss: lambda_o sum_i |o_i| and
+ * lambda_s sum_i sum_j |sqrt(eig_j(Sigma_i))| = lambda_s sum_i sum_j |s_ij|
+ * (Sigma = R diag(s^2) R^T).  ADDS lambda_o sign(o) to grads->opacities and
+ * lambda_s sign(s) to grads->scales (the other gradient pointers are not
+ * touched); loss (device float, may be NULL) is INCREMENTED by the value.
+ * The paper trains with lambda_o = lambda_s = 0.01. */
+dbs_status dbs_regularizer(const dbs_splats *splats /*[host] struct of device pointers*/, float lambda_o,
+                           float lambda_s, dbs_splat_grads *grads /*[host] struct of device pointers*/,
+                           float *loss, void *stream);
+
 /* ---- introspection (tests, profiling) ------------------------------------ */
 
 /* Device pointers into `projected` for n splats and n_views views:

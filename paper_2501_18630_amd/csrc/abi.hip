@@ -246,6 +246,28 @@ dbs_status dbs_l1_loss(const float *image, const float *target, int64_t count, f
     return hip_status(launch_l1_loss(image, target, count, scale, dL_dimage, loss, (hipStream_t)stream));
 }
 
+dbs_status dbs_photometric_loss(const float *image, const float *target, const dbs_camera *cams, int32_t n_views,
+                                float lambda_ssim, float *dL_dimage, float *loss, void *stream)
+{
+    DBS_TRY(check_cams(cams, n_views));
+    if (!image || !target || !dL_dimage) return DBS_ERR_INVALID_ARGUMENT;
+    if (!(lambda_ssim >= 0.0f && lambda_ssim <= 1.0f)) return DBS_ERR_INVALID_ARGUMENT;
+    return hip_status(launch_photometric_loss(image, target, cams, n_views, lambda_ssim, dL_dimage, loss,
+                                              (hipStream_t)stream));
+}
+
+dbs_status dbs_regularizer(const dbs_splats *splats, float lambda_o, float lambda_s, dbs_splat_grads *grads,
+                           float *loss, void *stream)
+{
+    DBS_TRY(check_splats(splats));
+    DBS_TRY(check_grads(splats, grads));
+    if (!finite(lambda_o) || !finite(lambda_s)) return DBS_ERR_INVALID_ARGUMENT;
+    GradPtrs g{};
+    g.opacities = grads->opacities;
+    g.scales = grads->scales;
+    return hip_status(launch_regularizer(splat_ptrs(splats), lambda_o, lambda_s, g, loss, (hipStream_t)stream));
+}
+
 dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views, void **record, void **bbox,
                                 void **depth, void **ntiles, void **counts)
 {

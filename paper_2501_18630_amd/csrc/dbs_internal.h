@@ -221,5 +221,10 @@ hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, 
                               hipStream_t s);
 hipError_t launch_l1_loss(const float *image, const float *target, int64_t count, float scale,
                           float *grad, float *loss, hipStream_t s);
+// loss.hip
+hipError_t launch_photometric_loss(const float *image, const float *target, const dbs_camera *cams,
+                                   int32_t n_views, float lam, float *grad, float *loss, hipStream_t s);
+hipError_t launch_regularizer(const SplatPtrs &sp, float lam_o, float lam_s, const GradPtrs &g, float *loss,
+                              hipStream_t s);
 
 }  // namespace dbs

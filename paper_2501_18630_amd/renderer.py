@@ -200,6 +200,22 @@ class Rasterizer:
             C.c_void_p(dL_dimage.data_ptr()), C.c_void_p(loss.data_ptr()) if loss is not None else None,
             _stream()))
 
+    def photometric_loss(self, image, target, lambda_ssim: float, dL_dimage, loss=None):
+        """(1 - lambda) L1 + lambda (1 - SSIM), summed over views (Sec. 3.4);
+        dL_dimage and loss are overwritten."""
+        check("dbs_photometric_loss", self.lib.dbs_photometric_loss(
+            C.c_void_p(image.data_ptr()), C.c_void_p(target.data_ptr()), self.cams_c, self.V,
+            float(lambda_ssim), C.c_void_p(dL_dimage.data_ptr()),
+            C.c_void_p(loss.data_ptr()) if loss is not None else None, _stream()))
+
+    def regularizer(self, params: dict, lambda_o: float, lambda_s: float, grads: dict, loss=None):
+        """lambda_o sum|o| + lambda_s sum|s| (Sec. 3.4): gradients added, loss incremented."""
+        sp = _splats_c(params, self.n, self.m)
+        gr = _grads_c(grads)
+        check("dbs_regularizer", self.lib.dbs_regularizer(
+            C.byref(sp), float(lambda_o), float(lambda_s), C.byref(gr),
+            C.c_void_p(loss.data_ptr()) if loss is not None else None, _stream()))
+
     # ---- views of the flat buffers ----
     def split_image(self, image):
         """flat planar image -> list of [3, H, W] views."""
@@ -284,15 +300,20 @@ def render(params: dict, rast: Rasterizer):
 
 
 class TrainStep:
-    """One fixed-size training step (forward, L1 loss to a target, backward)
-    over all views, captured once in a HIP graph and replayed.
+    """One fixed-size training step (forward, loss to a target, backward)
+    over all views, captured once in a HIP graph and replayed.  The loss is
+    L1 (mean over all channel-pixels) or, with `lambda_ssim` set, the
+    composite loss of Sec. 3.4: per view (1 - lambda) L1 + lambda (1 - SSIM),
+    plus lambda_o sum|o| + lambda_s sum|s|.
 
     The pair capacity is fixed at capture time from an eager run times
     `headroom`; a replay whose pair count exceeds it sets `overflow`, leaves
     every tile list empty, and `replay()` reports it so the caller can
     rebuild with a larger capacity."""
 
-    def __init__(self, rast: Rasterizer, params: dict, target, headroom: float = 1.1, use_graph=True):
+    def __init__(self, rast: Rasterizer, params: dict, target, headroom: float = 1.1, use_graph=True,
+                 lambda_ssim: float | None = None, lambda_o: float = 0.0, lambda_s: float = 0.0):
+        self.lambda_ssim, self.lambda_o, self.lambda_s = lambda_ssim, lambda_o, lambda_s
         self.rast = rast
         self.params = params
         self.target = target
@@ -323,10 +344,15 @@ class TrainStep:
         r.preprocess(self.params)
         r.bin_sort()
         r.render_fwd(self.image, self.final_T, self.last)
-        r.l1_loss(self.image, self.target, self.scale, self.dL, self.loss)
+        if self.lambda_ssim is None:
+            r.l1_loss(self.image, self.target, self.scale, self.dL, self.loss)
+        else:
+            r.photometric_loss(self.image, self.target, self.lambda_ssim, self.dL, self.loss)
         for g in self.grads.values():
             g.zero_()
         r.render_bwd(self.params, self.dL, self.final_T, self.last, self.grads)
+        if self.lambda_o or self.lambda_s:
+            r.regularizer(self.params, self.lambda_o, self.lambda_s, self.grads, self.loss)
 
     def run(self):
         if self.graph is not None:
