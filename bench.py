@@ -148,6 +148,33 @@ def composite_loss_times(rast, step, steps, lam_ssim=0.2, lam_reg=0.01):
     return t_p / steps, t_r / steps
 
 
+def mcmc_times(params, n, m, steps, tau=0.005):
+    """Average ms of the kernel-agnostic MCMC step of Sec. 3.4 over the scene
+    (relocation of primitives with o <= tau, positional noise), on a copy of
+    the parameters; not part of the benchmark step."""
+    import torch
+    from paper_2501_18630_amd import renderer
+    mc = renderer.MCMC(n, m)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    rand = torch.randint(-2**31, 2**31 - 1, (n,), dtype=torch.int32, device="cuda", generator=g)
+    z = torch.randn(n, 3, device="cuda", generator=g)
+    t_r = t_n = 0.0
+    moved = 0
+    for _ in range(steps):
+        p = {k: v.clone() for k, v in params.items()}
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        cnt = mc.relocate(p, tau, rand)
+        ev[1].record()
+        mc.noise(p, z, 0.01, 5e4)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_r += ev[0].elapsed_time(ev[1])
+        t_n += ev[1].elapsed_time(ev[2])
+        moved = int(cnt.item())
+    return t_r / steps, t_n / steps, moved
+
+
 def work_counts(rast, step):
     """Pair counts and evaluated / contributing (pixel, pair) counts of the
     last step, from the library's counting pass (outside the timed region)."""
@@ -252,6 +279,8 @@ def main():
     log(f"work: {wc}")
     t_photo, t_reg = composite_loss_times(rast, step, max(3, args.steps // 2))
     log(f"composite loss (ms): photometric {t_photo:.3f}, regularisers {t_reg:.3f}")
+    t_reloc, t_noise, n_moved = mcmc_times(params, n, m, 3)
+    log(f"mcmc (ms): relocate {t_reloc:.3f} ({n_moved} moved), noise {t_noise:.3f}")
 
     mpix = X / t_batched / 1e6
     q_floats = 15 + 6 * m
@@ -294,6 +323,8 @@ def main():
         # not in the step: the composite loss of the paper's training (lambda_SSIM = 0.2)
         "composite_loss": {"photometric_ms": round(t_photo, 4), "regularizer_ms": round(t_reg, 4),
                            "photometric_GBs": round(12 * 3 * X / (t_photo * 1e-3) / 1e9, 1)},
+        # not in the step: the MCMC step of Sec. 3.4 over all splats (dead: o <= 0.005)
+        "mcmc": {"relocate_ms": round(t_reloc, 4), "noise_ms": round(t_noise, 4), "relocated": n_moved},
         "work": wc,
     }
     if not args.no_cpu_baseline:

@@ -251,6 +251,42 @@ dbs_status dbs_regularizer(const dbs_splats *splats /*[host] struct of device po
                            float lambda_s, dbs_splat_grads *grads /*[host] struct of device pointers*/,
                            float *loss, void *stream);
 
+/* ---- kernel-agnostic MCMC step (Sec. 3.4) -------------------------------- */
+
+/* Splat parameters updated in place: the fields of dbs_splats, writable. */
+typedef struct {
+    float *means, *scales, *quats, *opacities, *betas, *diffuse;
+    float *lobe_angles, *lobe_colors, *lobe_betas;
+    int64_t n;
+    int32_t m;
+} dbs_splats_mut;
+
+/* Scratch for dbs_mcmc_relocate (about 24 bytes per splat). */
+size_t dbs_mcmc_workspace_bytes(int64_t n);
+
+/* Relocation of dead primitives (Densification paragraph of Sec. 3.4 and
+ * its appendix): a primitive with opacity <= dead_opacity is dead; each dead
+ * primitive i becomes a copy (every parameter) of a live primitive j drawn
+ * with probability proportional to its opacity, using rand[i] (uniform
+ * 32-bit, caller-supplied, [n]): with w_j = floor(o_j 2^24) and inclusive
+ * prefix sums P_j, j is the first index with P_j > floor(rand[i] W / 2^32),
+ * W = sum_j w_j.  A live primitive drawn N - 1 times and its N - 1 copies all
+ * get opacity 1 - (1 - o)^(1/N); no other parameter is adjusted.  Nothing
+ * moves when no primitive is live.  n_relocated (device int32, may be NULL)
+ * is OVERWRITTEN with the number of dead primitives moved.  Parameters are
+ * updated in place; the caller resets any optimiser state it keeps. */
+dbs_status dbs_mcmc_relocate(const dbs_splats_mut *splats /*[host] struct of device pointers*/,
+                             float dead_opacity, const uint32_t *rand, void *workspace, size_t workspace_bytes,
+                             int32_t *n_relocated, void *stream);
+
+/* Positional noise of the Optimization paragraph of Sec. 3.4:
+ *   mu += lambda_eps lr B(o; b') R diag(s) z,   B(o; b') = (1 - o)^(4 e^b'),
+ * z: [n,3] standard normals supplied by the caller (R diag(s) z is then a
+ * sample of N(0, Sigma)); the paper uses b' = ln 25.  Updates means in
+ * place; the other parameters are read. */
+dbs_status dbs_mcmc_noise(const dbs_splats_mut *splats /*[host] struct of device pointers*/, const float *z,
+                          float lr, float lambda_eps, float b_prime, void *stream);
+
 /* ---- introspection (tests, profiling) ------------------------------------ */
 
 /* Device pointers into `projected` for n splats and n_views views:

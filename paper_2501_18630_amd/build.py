@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdbs.so")
 ARCH = "gfx950"
 
-SOURCES = ["abi.hip", "preprocess.hip", "sort.hip", "raster.hip", "project_bwd.hip", "loss.hip"]
+SOURCES = ["abi.hip", "preprocess.hip", "sort.hip", "raster.hip", "project_bwd.hip", "loss.hip", "mcmc.hip"]
 
 # Packed FP32 instructions are disabled: hipcc would otherwise form them from
 # plain float code.  FP64 geometry is evaluated without contraction so that

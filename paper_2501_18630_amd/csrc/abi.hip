@@ -268,6 +268,50 @@ dbs_status dbs_regularizer(const dbs_splats *splats, float lambda_o, float lambd
     return hip_status(launch_regularizer(splat_ptrs(splats), lambda_o, lambda_s, g, loss, (hipStream_t)stream));
 }
 
+static dbs_status check_splats_mut(const dbs_splats_mut *s, SplatMut *out)
+{
+    if (!s || s->n < 0) return DBS_ERR_INVALID_ARGUMENT;
+    if (s->m < 0 || s->m > DBS_MAX_LOBES) return DBS_ERR_UNSUPPORTED;
+    if (s->n > 0) {
+        if (!s->means || !s->scales || !s->quats || !s->opacities || !s->betas || !s->diffuse)
+            return DBS_ERR_INVALID_ARGUMENT;
+        if (s->m > 0 && (!s->lobe_angles || !s->lobe_colors || !s->lobe_betas)) return DBS_ERR_INVALID_ARGUMENT;
+    }
+    out->means = s->means; out->scales = s->scales; out->quats = s->quats; out->opacities = s->opacities;
+    out->betas = s->betas; out->diffuse = s->diffuse; out->lobe_angles = s->lobe_angles;
+    out->lobe_colors = s->lobe_colors; out->lobe_betas = s->lobe_betas;
+    out->n = s->n; out->m = s->m;
+    return DBS_OK;
+}
+
+size_t dbs_mcmc_workspace_bytes(int64_t n)
+{
+    if (n < 0 || n > 0xffffffffll) return 0;
+    return mcmc_layout(n).total;
+}
+
+dbs_status dbs_mcmc_relocate(const dbs_splats_mut *splats, float dead_opacity, const uint32_t *rand, void *workspace,
+                             size_t workspace_bytes, int32_t *n_relocated, void *stream)
+{
+    SplatMut p;
+    DBS_TRY(check_splats_mut(splats, &p));
+    if (p.n >= 0xffffffffll) return DBS_ERR_UNSUPPORTED;
+    if (!finite(dead_opacity)) return DBS_ERR_INVALID_ARGUMENT;
+    if (p.n > 0 && (!rand || !workspace)) return DBS_ERR_INVALID_ARGUMENT;
+    if (p.n > 0 && workspace_bytes < mcmc_layout(p.n).total) return DBS_ERR_CAPACITY;
+    return hip_status(launch_mcmc_relocate(p, dead_opacity, rand, workspace, n_relocated, (hipStream_t)stream));
+}
+
+dbs_status dbs_mcmc_noise(const dbs_splats_mut *splats, const float *z, float lr, float lambda_eps, float b_prime,
+                          void *stream)
+{
+    SplatMut p;
+    DBS_TRY(check_splats_mut(splats, &p));
+    if (p.n > 0 && !z) return DBS_ERR_INVALID_ARGUMENT;
+    if (!finite(lr) || !finite(lambda_eps) || !finite(b_prime)) return DBS_ERR_INVALID_ARGUMENT;
+    return hip_status(launch_mcmc_noise(p, z, lr, lambda_eps, b_prime, (hipStream_t)stream));
+}
+
 dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views, void **record, void **bbox,
                                 void **depth, void **ntiles, void **counts)
 {

@@ -151,6 +151,22 @@ struct GradPtrs {
     float *lobe_angles, *lobe_colors, *lobe_betas;
 };
 
+// Splat parameters updated in place (MCMC step).
+struct SplatMut {
+    float *means, *scales, *quats, *opacities, *betas, *diffuse;
+    float *lobe_angles, *lobe_colors, *lobe_betas;
+    int64_t n;
+    int32_t m;
+};
+
+// Workspace of the MCMC relocation: per-block weight sums (+ total), inclusive
+// weight prefix sums, copy counts, draw targets, new opacities.
+struct McmcLayout {
+    int64_t nblocks;
+    size_t bsum, prefix, count, target, onew, total;
+};
+McmcLayout mcmc_layout(int64_t n);
+
 // Pointers into `projected`.
 struct ProjPtrs {
     ProjHeader *hdr;
@@ -221,6 +237,11 @@ hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, 
                               hipStream_t s);
 hipError_t launch_l1_loss(const float *image, const float *target, int64_t count, float scale,
                           float *grad, float *loss, hipStream_t s);
+// mcmc.hip
+hipError_t launch_mcmc_relocate(const SplatMut &p, float tau, const uint32_t *rand, void *work, int32_t *n_relocated,
+                                hipStream_t s);
+hipError_t launch_mcmc_noise(const SplatMut &p, const float *z, float lr, float lambda_eps, float b_prime,
+                             hipStream_t s);
 // loss.hip
 hipError_t launch_photometric_loss(const float *image, const float *target, const dbs_camera *cams,
                                    int32_t n_views, float lam, float *grad, float *loss, hipStream_t s);

@@ -299,6 +299,34 @@ def render(params: dict, rast: Rasterizer):
     return _RenderFn.apply(rast, *[params[k] for k in PARAMS])
 
 
+class MCMC:
+    """Kernel-agnostic MCMC step of Sec. 3.4 on device parameter tensors
+    (updated in place): relocation of dead primitives and positional noise.
+    Random numbers are inputs: 32-bit uniforms for the draws, standard
+    normals for the noise."""
+
+    def __init__(self, n: int, m: int, device="cuda"):
+        self.lib = _lib.load()
+        self.n, self.m = int(n), int(m)
+        wb = self.lib.dbs_mcmc_workspace_bytes(self.n)
+        self.workspace = torch.empty(max(wb, 1), dtype=torch.uint8, device=device)
+        self.relocated = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def relocate(self, params: dict, dead_opacity: float, rand):
+        """rand: int32/uint32 tensor [n] of uniform bits.  Returns the device
+        count of moved primitives (no host sync)."""
+        sp = _splats_c(params, self.n, self.m)
+        check("dbs_mcmc_relocate", self.lib.dbs_mcmc_relocate(
+            C.byref(sp), float(dead_opacity), C.c_void_p(rand.data_ptr()), C.c_void_p(self.workspace.data_ptr()),
+            self.workspace.numel(), C.c_void_p(self.relocated.data_ptr()), _stream()))
+        return self.relocated
+
+    def noise(self, params: dict, z, lr: float, lambda_eps: float, b_prime: float = float(np.log(25.0))):
+        sp = _splats_c(params, self.n, self.m)
+        check("dbs_mcmc_noise", self.lib.dbs_mcmc_noise(
+            C.byref(sp), C.c_void_p(z.data_ptr()), float(lr), float(lambda_eps), float(b_prime), _stream()))
+
+
 class TrainStep:
     """One fixed-size training step (forward, loss to a target, backward)
     over all views, captured once in a HIP graph and replayed.  The loss is
