@@ -106,6 +106,7 @@ typedef struct {
     float t_eps;           /* default 1e-4 */
     float alpha_max;       /* default 0.99; must lie in (0, 1) */
     uint32_t flags;        /* DBS_FLAG_* */
+    float b_split;         /* threshold of DBS_FLAG_B_BELOW / DBS_FLAG_B_ABOVE, default 0 */
 } dbs_raster_cfg;
 
 /* Raster kernels run persistently: a fixed grid drains a device-side queue
@@ -113,7 +114,21 @@ typedef struct {
  * workgroup is launched per work item. */
 #define DBS_FLAG_PERSISTENT 1u
 
-/* Fills *cfg with the defaults above (16x16 tiles, batch 256, persistent). */
+/* Decomposition render modes (Beta Decomposition section of the paper),
+ * applied by dbs_preprocess; forward rendering only (the reverse calls
+ * reject them with DBS_ERR_UNSUPPORTED).
+ *   DIFFUSE_ONLY:  colour = c0 (the base colour; lighting decomposition)
+ *   SPECULAR_ONLY: colour = the Spherical Beta lobes without c0
+ *   B_BELOW / B_ABOVE: only primitives with b < b_split / b >= b_split
+ *                  (geometry decomposition by the kernel shape b).
+ * DIFFUSE_ONLY with SPECULAR_ONLY, or B_BELOW with B_ABOVE, is invalid. */
+#define DBS_FLAG_DIFFUSE_ONLY 2u
+#define DBS_FLAG_SPECULAR_ONLY 4u
+#define DBS_FLAG_B_BELOW 8u
+#define DBS_FLAG_B_ABOVE 16u
+
+/* Fills *cfg with the defaults above (16x16 tiles, batch 256, persistent, no
+ * decomposition). */
 void dbs_default_cfg(dbs_raster_cfg *cfg);
 
 /* ---- buffer sizes (bytes) ---------------------------------------------- */
@@ -261,7 +276,7 @@ typedef struct {
     int32_t m;
 } dbs_splats_mut;
 
-/* Scratch for dbs_mcmc_relocate (about 24 bytes per splat). */
+/* Scratch for dbs_mcmc_relocate (about 20 bytes per splat). */
 size_t dbs_mcmc_workspace_bytes(int64_t n);
 
 /* Relocation of dead primitives (Densification paragraph of Sec. 3.4 and

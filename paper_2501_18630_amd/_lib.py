@@ -16,6 +16,10 @@ OK, ERR_INVALID_ARGUMENT, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED = range(5)
 MAX_LOBES = 8
 MAX_VIEWS = 1024
 FLAG_PERSISTENT = 1
+FLAG_DIFFUSE_ONLY = 2
+FLAG_SPECULAR_ONLY = 4
+FLAG_B_BELOW = 8
+FLAG_B_ABOVE = 16
 
 PARAMS = ("means", "scales", "quats", "opacities", "betas", "diffuse",
           "lobe_angles", "lobe_colors", "lobe_betas")
@@ -50,7 +54,7 @@ class Camera(C.Structure):
 
 class RasterCfg(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("batch", C.c_int32),
-                ("t_eps", C.c_float), ("alpha_max", C.c_float), ("flags", C.c_uint32)]
+                ("t_eps", C.c_float), ("alpha_max", C.c_float), ("flags", C.c_uint32), ("b_split", C.c_float)]
 
 
 _lib = None

@@ -39,7 +39,12 @@ static dbs_status check_cfg(const dbs_raster_cfg *cfg)
     if (!cfg) return DBS_ERR_INVALID_ARGUMENT;
     if (!(cfg->alpha_max > 0.0f && cfg->alpha_max < 1.0f)) return DBS_ERR_INVALID_ARGUMENT;
     if (!(cfg->t_eps >= 0.0f && cfg->t_eps < 1.0f)) return DBS_ERR_INVALID_ARGUMENT;
-    if ((cfg->flags & ~DBS_FLAG_PERSISTENT) != 0) return DBS_ERR_INVALID_ARGUMENT;
+    const uint32_t known = DBS_FLAG_PERSISTENT | DBS_FLAG_DIFFUSE_ONLY | DBS_FLAG_SPECULAR_ONLY | DBS_FLAG_B_BELOW |
+                           DBS_FLAG_B_ABOVE;
+    if ((cfg->flags & ~known) != 0) return DBS_ERR_INVALID_ARGUMENT;
+    if ((cfg->flags & DBS_FLAG_DIFFUSE_ONLY) && (cfg->flags & DBS_FLAG_SPECULAR_ONLY)) return DBS_ERR_INVALID_ARGUMENT;
+    if ((cfg->flags & DBS_FLAG_B_BELOW) && (cfg->flags & DBS_FLAG_B_ABOVE)) return DBS_ERR_INVALID_ARGUMENT;
+    if (!finite(cfg->b_split)) return DBS_ERR_INVALID_ARGUMENT;
     if (!raster_supported(cfg->tile_w, cfg->tile_h, cfg->batch)) return DBS_ERR_UNSUPPORTED;
     return DBS_OK;
 }
@@ -74,6 +79,9 @@ static SplatPtrs splat_ptrs(const dbs_splats *s)
     return p;
 }
 
+constexpr uint32_t kDecompositionFlags = DBS_FLAG_DIFFUSE_ONLY | DBS_FLAG_SPECULAR_ONLY | DBS_FLAG_B_BELOW |
+                                         DBS_FLAG_B_ABOVE;
+
 static dbs_status hip_status(hipError_t e) { return e == hipSuccess ? DBS_OK : DBS_ERR_HIP; }
 
 #define DBS_TRY(x)                      \
@@ -97,6 +105,7 @@ void dbs_default_cfg(dbs_raster_cfg *cfg)
     cfg->t_eps = 1e-4f;
     cfg->alpha_max = 0.99f;
     cfg->flags = DBS_FLAG_PERSISTENT;
+    cfg->b_split = 0.0f;
 }
 
 size_t dbs_projected_bytes(int64_t n, int32_t n_views)
@@ -131,7 +140,8 @@ dbs_status dbs_preprocess(const dbs_splats *splats, const dbs_camera *cams, int3
     hipStream_t s = (hipStream_t)stream;
     ProjPtrs P = proj_ptrs(projected, splats->n, n_views);
     DBS_TRY(hip_status(launch_upload_views(cams, n_views, cfg->tile_w, cfg->tile_h, P, splats->n, splats->m, s)));
-    return hip_status(launch_preprocess(splat_ptrs(splats), P, n_views, cfg->tile_w, cfg->tile_h, counts, s));
+    return hip_status(launch_preprocess(splat_ptrs(splats), P, n_views, cfg->tile_w, cfg->tile_h, cfg->flags,
+                                        cfg->b_split, counts, s));
 }
 
 dbs_status dbs_bin_sort(const void *projected, const dbs_camera *cams, int32_t n_views, const dbs_raster_cfg *cfg,
@@ -187,6 +197,7 @@ dbs_status dbs_raster_bwd(const void *projected, const void *bins, const dbs_cam
 {
     DBS_TRY(check_cams(cams, n_views));
     DBS_TRY(check_cfg(cfg));
+    if (cfg->flags & kDecompositionFlags) return DBS_ERR_UNSUPPORTED;
     DBS_TRY(check_sizes(n, n_views));
     if (!projected || !bins || !final_T || !last_index || !dL_dimage) return DBS_ERR_INVALID_ARGUMENT;
     const int64_t n_tiles = total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h);
@@ -202,6 +213,7 @@ dbs_status dbs_project_bwd(const dbs_splats *splats, const void *projected, cons
     DBS_TRY(check_splats(splats));
     DBS_TRY(check_cams(cams, n_views));
     DBS_TRY(check_cfg(cfg));
+    if (cfg->flags & kDecompositionFlags) return DBS_ERR_UNSUPPORTED;
     DBS_TRY(check_sizes(splats->n, n_views));
     if (!projected) return DBS_ERR_INVALID_ARGUMENT;
     DBS_TRY(check_grads(splats, grads));

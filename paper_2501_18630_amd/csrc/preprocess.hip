@@ -53,7 +53,7 @@ __device__ inline uint64_t wave_sum_u64(uint64_t v)
 
 template <int M>
 __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
-                                                         int32_t lw, int32_t lh)
+                                                         int32_t lw, int32_t lh, uint32_t flags, float b_split)
 {
     const int64_t n = sp.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,6 +65,10 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
                q3 = sp.quats[4 * i + 3];
         double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
         bool ok = qn > 0.0;
+        // geometry decomposition: primitives outside the b range are culled in every view
+        if (flags & DBS_FLAG_B_BELOW) ok = ok && sp.betas[i] < b_split;
+        if (flags & DBS_FLAG_B_ABOVE) ok = ok && sp.betas[i] >= b_split;
+        const bool diffuse_on = !(flags & DBS_FLAG_SPECULAR_ONLY), specular_on = !(flags & DBS_FLAG_DIFFUSE_ONLY);
         double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
         double Rq[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
                         2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
@@ -85,7 +89,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
             }
         const float opac = sp.opacities[i];
         const float beta = 4.0f * expf(sp.betas[i]);
-        const float c0r = sp.diffuse[3 * i], c0g = sp.diffuse[3 * i + 1], c0b = sp.diffuse[3 * i + 2];
+        const float c0r = diffuse_on ? sp.diffuse[3 * i] : 0.0f, c0g = diffuse_on ? sp.diffuse[3 * i + 1] : 0.0f,
+                    c0b = diffuse_on ? sp.diffuse[3 * i + 2] : 0.0f;
         float lr[M > 0 ? M : 1][3], lc[M > 0 ? M : 1][3], lbeta[M > 0 ? M : 1];
 #pragma unroll
         for (int mm = 0; mm < M; ++mm) {
@@ -166,7 +171,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
 #pragma unroll
                         for (int mm = 0; mm < M; ++mm) {
                             const float d = lr[mm][0] * dx + lr[mm][1] * dy + lr[mm][2] * dz;
-                            if (d > 0.0f) {
+                            if (specular_on && d > 0.0f) {
                                 const float wgt = exp2f(lbeta[mm] * log2f(d));
                                 cr += wgt * lc[mm][0];
                                 cg += wgt * lc[mm][1];
@@ -238,8 +243,8 @@ hipError_t launch_upload_views(const dbs_camera *cams, int32_t n_views, int tile
     return hipGetLastError();
 }
 
-hipError_t launch_preprocess(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, int tile_w,
-                             int tile_h, int64_t *counts_out, hipStream_t s)
+hipError_t launch_preprocess(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, int tile_w, int tile_h,
+                             uint32_t flags, float b_split, int64_t *counts_out, hipStream_t s)
 {
     if (sp.n > 0) {
         // tile sizes are powers of two: pixel -> tile is a shift
@@ -249,7 +254,7 @@ hipError_t launch_preprocess(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, i
         if ((1 << lw) != tile_w || (1 << lh) != tile_h) return hipErrorInvalidValue;
         dim3 grid((unsigned)ceil_div(sp.n, 256));
         switch (sp.m) {
-#define DBS_PRE(MM) case MM: preprocess_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, lw, lh); break;
+#define DBS_PRE(MM) case MM: preprocess_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, lw, lh, flags, b_split); break;
             DBS_PRE(0) DBS_PRE(1) DBS_PRE(2) DBS_PRE(3) DBS_PRE(4)
             DBS_PRE(5) DBS_PRE(6) DBS_PRE(7) DBS_PRE(8)
 #undef DBS_PRE

@@ -34,10 +34,17 @@ class RasterConfig:
     t_eps: float = 1e-4
     alpha_max: float = 0.99
     persistent: bool = True
+    # decomposition render modes (forward only): "diffuse" / "specular" colour,
+    # and primitives with b below / at-or-above b_split
+    color: str = "full"
+    b_range: str = "all"
+    b_split: float = 0.0
 
     def to_c(self) -> _lib.RasterCfg:
-        return _lib.RasterCfg(self.tile_w, self.tile_h, self.batch, self.t_eps, self.alpha_max,
-                              _lib.FLAG_PERSISTENT if self.persistent else 0)
+        flags = _lib.FLAG_PERSISTENT if self.persistent else 0
+        flags |= {"full": 0, "diffuse": _lib.FLAG_DIFFUSE_ONLY, "specular": _lib.FLAG_SPECULAR_ONLY}[self.color]
+        flags |= {"all": 0, "below": _lib.FLAG_B_BELOW, "above": _lib.FLAG_B_ABOVE}[self.b_range]
+        return _lib.RasterCfg(self.tile_w, self.tile_h, self.batch, self.t_eps, self.alpha_max, flags, self.b_split)
 
 
 def make_cameras(cams) -> C.Array:

@@ -60,6 +60,20 @@ def test_host_only_queries(lib):
     assert lib.dbs_bin_sort(None, cams, 2, C.byref(cfg), 10, 10, None, 0, None, 0, None, None) \
         == _lib.ERR_INVALID_ARGUMENT
     assert lib.dbs_l1_loss(None, None, -1, 1.0, None, None, None) == _lib.ERR_INVALID_ARGUMENT
+    # decomposition modes: exclusive pairs are rejected, single modes accepted
+    for flags, ok in ((_lib.FLAG_DIFFUSE_ONLY, True), (_lib.FLAG_B_ABOVE | _lib.FLAG_SPECULAR_ONLY, True),
+                      (_lib.FLAG_DIFFUSE_ONLY | _lib.FLAG_SPECULAR_ONLY, False),
+                      (_lib.FLAG_B_BELOW | _lib.FLAG_B_ABOVE, False), (32, False)):
+        c2 = _lib.RasterCfg(16, 16, 256, 1e-4, 0.99, _lib.FLAG_PERSISTENT | flags, 0.5)
+        assert (lib.dbs_bins_bytes(10, cams, 2, C.byref(c2)) > 0) == ok, flags
+    c2 = _lib.RasterCfg(16, 16, 256, 1e-4, 0.99, _lib.FLAG_PERSISTENT, float("nan"))
+    assert lib.dbs_bins_bytes(10, cams, 2, C.byref(c2)) == 0
+    # loss and MCMC entry points validate before touching a device
+    assert lib.dbs_photometric_loss(None, None, cams, 2, 0.2, None, None, None) == _lib.ERR_INVALID_ARGUMENT
+    assert lib.dbs_mcmc_workspace_bytes(1000) >= 1000 * 20
+    sp = _lib.Splats(*([None] * 9), 10, 2)
+    assert lib.dbs_mcmc_noise(C.byref(sp), None, 0.1, 1.0, 3.2, None) == _lib.ERR_INVALID_ARGUMENT
+    assert lib.dbs_mcmc_relocate(C.byref(sp), 0.005, None, None, 0, None, None) == _lib.ERR_INVALID_ARGUMENT
 
 
 def test_no_cpu_fallback_when_library_missing(tmp_path):

@@ -387,3 +387,32 @@ def test_backward_lobes_nearly_aligned_with_view(oracle):
     g, a = oracle.render_bwd(s, cam, float(AMAX), float(TEPS), hw3(dl[0]), want_abs=True)
     assert np.count_nonzero(g["lobe_betas"][:, 0]) >= 12
     assert_grads_close(out["grads"], g, a)
+
+
+
+def test_decomposition_render_modes(oracle):
+    """Diffuse-only / specular-only colour and b-split geometry (the paper's
+    Beta Decomposition) equal plain renders of the correspondingly edited
+    scene, bit for bit, and the oracle's; the reverse calls reject them."""
+    from paper_2501_18630_amd import _lib
+    from paper_2501_18630_amd.renderer import RasterConfig
+    s = tiny_scene(500, 41, m=2)
+    cams = [scenes.look_at_camera([0.5, 0.3, -5.0], 75, 53), scenes.camera(37, 29, f=30.0)]
+    split = float(np.median(s["betas"]))
+    cases = [(dict(color="diffuse"), {**s, "lobe_colors": np.zeros_like(s["lobe_colors"])}),
+             (dict(color="specular"), {**s, "diffuse": np.zeros_like(s["diffuse"])}),
+             (dict(b_range="below", b_split=split), scenes.subset(s, np.nonzero(s["betas"] < split)[0])),
+             (dict(b_range="above", b_split=split, color="specular"),
+              scenes.subset({**s, "diffuse": np.zeros_like(s["diffuse"])}, np.nonzero(s["betas"] >= split)[0]))]
+    for kw, edited in cases:
+        got = gpu_render(s, cams, RasterConfig(**kw))
+        ref = gpu_render(edited, cams)
+        for v, cam in enumerate(cams):
+            np.testing.assert_array_equal(got["images"][v], ref["images"][v], err_msg=str(kw))
+            o = oracle_view(oracle, edited, cam)
+            assert_image_close(hw3(got["images"][v]), o["rgb"], o["T"], o["T_prev"])
+    import torch
+    out = gpu_render(s, cams, RasterConfig(color="diffuse"))
+    grads = {k: torch.zeros_like(out["params"][k]) for k in PARAMS}
+    with pytest.raises(_lib.DbsError):
+        out["rast"].backward(out["params"], torch.zeros_like(out["image_t"]), out["T_t"], out["last_t"], grads)
