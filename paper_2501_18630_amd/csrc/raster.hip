@@ -279,9 +279,9 @@ __device__ __forceinline__ int max4(const int v[4]) { return max(max(v[0], v[1])
 
 // Reverse walk: at step s row r takes entry cnt[r] - 1 - s of its list.  Rows
 // that take the same splat at the same step would add to the same LDS slot, so
-// their sums are merged first and only the lowest such row stores.  Nibble r of
-// share[s]: bit 0/1/2 = row r's splat is also that of row r^1 / r^2 / r^3,
-// bit 3 = another, lower row stores for row r.
+// their sums are merged first and only the lowest such row stores.  Bit
+// 4e + r of share[s], e = 0/1/2: row r's splat is also that of row r^(e+1);
+// bit 12 + r: another, lower row stores for row r.  Zero: no two rows share.
 template <int BATCH>
 __device__ __forceinline__ void mark_shared_steps(const uint8_t *rows, const int cnt[4], int steps, uint16_t *share,
                                                   int lane)
@@ -299,7 +299,8 @@ __device__ __forceinline__ void mark_shared_steps(const uint8_t *rows, const int
         for (int r = 0; r < 4; ++r) {
             const bool e1 = kk[r] == kk[r ^ 1], e2 = kk[r] == kk[r ^ 2], e3 = kk[r] == kk[r ^ 3];
             const bool below = (e1 && (r ^ 1) < r) || (e2 && (r ^ 2) < r) || (e3 && (r ^ 3) < r);
-            word |= (uint32_t)(e1 | (e2 << 1) | (e3 << 2) | (below << 3)) << (4 * r);
+            word |= ((uint32_t)e1 << r) | ((uint32_t)e2 << (4 + r)) | ((uint32_t)e3 << (8 + r)) |
+                    ((uint32_t)below << (12 + r));
         }
         if (st < steps) share[st] = (uint16_t)word;
     }
@@ -472,17 +473,19 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 build_rows<BATCH>(S, s_blist[w], cnt_b, P.bx, P.by, lo, row_last, s_rows[w], cnt, lane);
                 const int my_cnt = pick4(cnt, P.row), steps = max4(cnt);
                 mark_shared_steps<BATCH>(s_rows[w], cnt, steps, s_share[w], lane);
+                // list entries are read one step ahead
+                int kl_next = my_row[my_cnt > 0 ? my_cnt - 1 : 0];  // in bounds either way
                 for (int step = 0; step < steps; ++step) {
                     const int t = my_cnt - 1 - step;  // back to front
                     const bool has = t >= 0;
-                    const int kl = my_row[has ? t : 0];  // in bounds either way
-                    const int k = has ? kl : 0;
+                    const int k = has ? kl_next : 0;
+                    kl_next = my_row[t > 0 ? t - 1 : 0];
                     const int32_t j = (int32_t)(lo + k);
                     const bool owner = fld >= 0 && has;
                     float *dst = &s_g[w][k][fld < 0 ? 0 : fld];
                     // read early: the slot's running sum, added to at the end of the step
                     const float prev = owner ? *dst : 0.0f;
-                    const uint32_t share = s_share[w][step];
+                    const uint32_t share = __builtin_amdgcn_readfirstlane(s_share[w][step]);
                     const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
                     const double dxd = fpx - c.x, dyd = fpy - c.y;
                     const double r2 = eval_r2(dxd, dyd, aa.x, aa.y, bb.x);
@@ -528,13 +531,16 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                     float tot = row_reduce10(v, lane);
                     // A row holds a splat at most once in its list: only rows taking the
                     // same splat in this step share a slot.  Merge theirs, lowest stores.
-                    const uint32_t nib = share >> (4 * P.row);
-                    if (share & 0x7777u) {
-                        const float x2 = from_row_xor2(tot, P.row);
-                        const float x1 = from_row_xor1(tot, P.row), x3 = from_row_xor1(x2, P.row);
-                        tot += ((nib & 1u) ? x1 : 0.0f) + ((nib & 2u) ? x2 : 0.0f) + ((nib & 4u) ? x3 : 0.0f);
+                    bool store = owner;
+                    if (share) {
+                        const float x1 = from_lane(tot, lane ^ 16), x2 = from_lane(tot, lane ^ 32);
+                        const float x3 = from_lane(tot, lane ^ 48);
+                        tot += (lane_in(kRowLanes.m[share & 15u]) ? x1 : 0.0f) +
+                               (lane_in(kRowLanes.m[(share >> 4) & 15u]) ? x2 : 0.0f) +
+                               (lane_in(kRowLanes.m[(share >> 8) & 15u]) ? x3 : 0.0f);
+                        store = store && !lane_in(kRowLanes.m[share >> 12]);
                     }
-                    if (owner && !(nib & 8u)) *dst = prev + tot;
+                    if (store) *dst = prev + tot;
                 }
                 __syncthreads();
                 // per (tile, splat): apply the per-splat factors.

@@ -114,21 +114,32 @@ __device__ __forceinline__ int row10_field(int lane)
     return f == 15 ? -1 : f;
 }
 
-// Value of x held by the same lane position in row r^1 / r^2 (v_permlane16_swap
-// exchanges odd rows of its first operand with even rows of its second,
-// v_permlane32_swap the upper half of the first with the lower of the second).
-__device__ __forceinline__ float from_row_xor1(float x, int row)
+// Value of x held by lane src_lane (ds_bpermute: a crossbar read through the
+// LDS unit, no VALU work and no LDS storage).
+__device__ __forceinline__ float from_lane(float x, int src_lane)
 {
-    const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, x),
-                                                   false, false);
-    return __builtin_bit_cast(float, (unsigned)((row & 1) ? r[0] : r[1]));
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src_lane << 2, __builtin_bit_cast(int, x)));
 }
 
-__device__ __forceinline__ float from_row_xor2(float x, int row)
+// kRowLanes.m[n]: 64-bit lane mask of the 16-lane rows whose bit is set in n
+// (bit r: lanes 16r .. 16r+15).  A table in constant memory: a wave-uniform n
+// turns into one scalar load instead of a chain of scalar shifts and masks.
+struct RowLaneTable {
+    uint64_t m[16];
+};
+
+constexpr RowLaneTable make_row_lane_table()
 {
-    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, x),
-                                                   false, false);
-    return __builtin_bit_cast(float, (unsigned)((row & 2) ? r[0] : r[1]));
+    RowLaneTable t{};
+    for (int n = 0; n < 16; ++n)
+        for (int r = 0; r < 4; ++r)
+            if (n & (1 << r)) t.m[n] |= 0xFFFFull << (16 * r);
+    return t;
 }
+
+static __constant__ RowLaneTable kRowLanes = make_row_lane_table();
+
+// True in the lanes whose bit of the wave-uniform mask m is set.
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
 }  // namespace dbs
