@@ -2,7 +2,10 @@
 
 For a given set of views and scene size it times the whole graph-captured
 training step (preprocess -> bin/sort -> forward -> L1 -> backward) for every
-built (tile_w, tile_h, batch) and keeps the fastest.  Results are cached in a
+built (tile_w, tile_h, batch), then re-times the few fastest with more steps,
+in alternating order, and keeps the fastest of those.  A warm-up run of the
+first shape precedes the sweep so that the first shapes timed are not
+charged for clock ramp-up.  Results are cached in a
 JSON file keyed by the GPU architecture, the view resolutions and the splat
 and lobe counts, so a workload is tuned once per machine type.
 
@@ -67,7 +70,7 @@ def time_config(cams, params, target, cfg: renderer.RasterConfig, steps: int = 3
 
 
 def tune(cams, params, target, candidates=None, batches=None, cache_path: str | None = CACHE,
-         steps: int = 3, log=None) -> renderer.RasterConfig:
+         steps: int = 3, refine: int = 3, log=None) -> renderer.RasterConfig:
     """Fastest RasterConfig for this workload (cached)."""
     n = params["means"].shape[0]
     m = params["lobe_betas"].shape[1]
@@ -76,14 +79,25 @@ def tune(cams, params, target, candidates=None, batches=None, cache_path: str | 
     if key in cache:
         e = cache[key]
         return renderer.RasterConfig(tile_w=e["tile_w"], tile_h=e["tile_h"], batch=e["batch"])
-    best, best_t, table = None, float("inf"), []
-    for tw, th in candidates or CANDIDATES:
-        for b in batches or BATCHES:
-            cfg = renderer.RasterConfig(tile_w=tw, tile_h=th, batch=b)
-            t = time_config(cams, params, target, cfg, steps=steps)
-            table.append({"tile_w": tw, "tile_h": th, "batch": b, "ms": round(t * 1e3, 4)})
+    shapes = [(tw, th, b) for tw, th in candidates or CANDIDATES for b in batches or BATCHES]
+    tw, th, b = shapes[0]
+    time_config(cams, params, target, renderer.RasterConfig(tile_w=tw, tile_h=th, batch=b), steps=4 * steps)
+    table = []
+    for tw, th, b in shapes:
+        t = time_config(cams, params, target, renderer.RasterConfig(tile_w=tw, tile_h=th, batch=b), steps=steps)
+        table.append({"tile_w": tw, "tile_h": th, "batch": b, "ms": round(t * 1e3, 4)})
+        if log:
+            log(f"autotune {tw}x{th} batch {b}: {t * 1e3:.3f} ms")
+    # second round over the fastest few: best of two longer runs each
+    finalists = sorted(table, key=lambda e: e["ms"])[:refine]
+    best, best_t = None, float("inf")
+    for rnd in range(2):
+        for e in (finalists if rnd == 0 else finalists[::-1]):
+            cfg = renderer.RasterConfig(tile_w=e["tile_w"], tile_h=e["tile_h"], batch=e["batch"])
+            t = time_config(cams, params, target, cfg, steps=4 * steps)
+            e["refined_ms"] = round(min(t * 1e3, e.get("refined_ms", float("inf"))), 4)
             if log:
-                log(f"autotune {tw}x{th} batch {b}: {t * 1e3:.3f} ms")
+                log(f"autotune refine {cfg.tile_w}x{cfg.tile_h} batch {cfg.batch}: {t * 1e3:.3f} ms")
             if t < best_t:
                 best, best_t = cfg, t
     if cache_path:
