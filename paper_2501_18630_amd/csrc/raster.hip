@@ -448,7 +448,8 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
         // last positions come from the forward over the same lists; keep them
         // inside this tile's range so that no pair outside it is ever read
         if (last >= (int32_t)it.end) last = (int32_t)it.end - 1;
-        float S0 = T * V.bg[0], S1 = T * V.bg[1], S2 = T * V.bg[2];
+        // g . S, S the colour composited behind the current splat (background included)
+        float gS = g0 * (T * V.bg[0]) + g1 * (T * V.bg[1]) + g2 * (T * V.bg[2]);
         if (tid == 0) s_maxlast = -1;
         __syncthreads();
         const int32_t wave_last = wave_max_i32(last);
@@ -506,12 +507,9 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                     const float wgt = alpha * Ti;
                     const float4 cc = s_col[k];
                     const float gc = g0 * cc.x + g1 * cc.y + g2 * cc.z;
-                    const float gS = g0 * S0 + g1 * S1 + g2 * S2;
                     const float dLda = Ti * gc - inv * gS;
-                    S0 = __fmaf_rn(cc.x, wgt, S0);
-                    S1 = __fmaf_rn(cc.y, wgt, S1);
-                    S2 = __fmaf_rn(cc.z, wgt, S2);
-                    T = contrib ? Ti : T;
+                    gS = __fmaf_rn(gc, wgt, gS);
+                    T = Ti;  // a lane not taking part has alpha = 0, inv = 1 exactly
                     // per-splat factors (o, beta, A) are applied once after the sums
                     const float t1 = (contrib && !clamped) ? dLda * B : 0.0f;
                     const float gp = t1 * __builtin_amdgcn_rcpf(omr);
