@@ -1,76 +1,26 @@
-// Cross-lane sums of ten per-lane floats (gfx950): over a whole 64-lane
-// wavefront (wave_reduce10), or over each 16-lane row (row_reduce10).
-//
-// wave_reduce10:
-// A multi-value butterfly: each exchange step halves the number of live
-// registers, so ten values cost 5 + 3 swaps and 12 row-local DPP adds instead
-// of 10 x 6 cross-lane shuffles.
-//   1. v_permlane32_swap pairs (v0,v1) (v2,v3) (v4,v5) (v6,v7) (v8,v9):
-//      afterwards register k holds partial sums of v_2k in lanes 0-31 and of
-//      v_2k+1 in lanes 32-63.
-//   2. v_permlane16_swap pairs those registers again; each 16-lane row of a
-//      register then holds partial sums of one field:
-//        s0 rows (v0, v2, v1, v3), s1 rows (v4, v6, v5, v7), s2 rows (v8, -, v9, -).
-//   3. DPP row_ror 8, 4, 2, 1 sums inside every row.
-// On return every lane of row r holds the totals of fields
-// field0(r) = {0, 2, 1, 3}[r] in out[0], field0(r) + 4 in out[1], and for even
-// rows 8 + r/2 in out[2].  Must be called with all 64 lanes active.
+// Cross-lane sums of ten per-lane floats over each 16-lane row of a
+// wavefront (row_reduce10, gfx950), and the helpers that merge row totals
+// across rows.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace dbs {
 
-__device__ __forceinline__ float row_sum16(float x)
-{
-    // row_ror:n has DPP control 0x120 + n
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x128, 0xf, 0xf, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x124, 0xf, 0xf, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x122, 0xf, 0xf, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x121, 0xf, 0xf, false));
-    return x;
-}
-
-__device__ __forceinline__ float swap32_add(float a, float b)
-{
-    auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
-                                             false, false);
-    return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
-}
-
-__device__ __forceinline__ float swap16_add(float a, float b)
-{
-    auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
-                                             false, false);
-    return __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
-}
-
-__device__ __forceinline__ void wave_reduce10(const float v[10], float out[3])
-{
-    const float r0 = swap32_add(v[0], v[1]);
-    const float r1 = swap32_add(v[2], v[3]);
-    const float r2 = swap32_add(v[4], v[5]);
-    const float r3 = swap32_add(v[6], v[7]);
-    const float r4 = swap32_add(v[8], v[9]);
-    out[0] = row_sum16(swap16_add(r0, r1));
-    out[1] = row_sum16(swap16_add(r2, r3));
-    out[2] = row_sum16(swap16_add(r4, 0.0f));
-}
-
-// Field held in out[0] by the lanes of 16-lane row `row` (out[1]: +4; out[2]: 8 + row/2 for even rows).
-__device__ __forceinline__ int reduce10_field0(int row) { return ((row & 1) << 1) | (row >> 1); }
-
-// row_reduce10: the same halving idea inside each 16-lane row, with DPP
-// exchanges only (no cross-row traffic).  At exchange distance 8 (row_ror:8),
-// 4 (row_half_mirror), 2 and 1 (quad_perm xor 2, xor 1) a pair of registers
+// row_reduce10: a multi-value butterfly inside each 16-lane row, with DPP
+// exchanges only (no cross-row traffic): each exchange halves the number of
+// live registers, so ten values do not cost ten separate row sums.  At
+// exchange distance 8 (row_ror:8), 4 (row_half_mirror), 2 and 1 (quad_perm
+// xor 2, xor 1) a pair of registers
 // (a, b) becomes one: lanes of the lower half of each exchanged pair keep
 // a + partner's a, lanes of the upper half b + partner's b.  Every exchange
 // pairs lanes that hold the same value with disjoint sets of summed lanes, so
 // after four exchanges each lane holds a full row total.  Ten values:
-// 5 + 2 + 1 + 1 halvings (3 VALU each) and 2 plain adds, 29 VALU in all.
+// 5 + 2 + 1 + 1 halvings and 2 folds; the halvings at distance 8 and 4 take
+// two bank-masked DPP adds each, those at 2 and 1 three VALU: 22 VALU in all.
 // On return lane l of a row holds the row total of value row10_field(l)
 // (-1: a duplicate, not to be stored); each value has exactly one owner.
-constexpr int kDppRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
+constexpr int kDppXor2 = 0x4E, kDppXor1 = 0xB1;  // quad_perm [2,3,0,1], [1,0,3,2]
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_partner(float x)
@@ -89,17 +39,37 @@ __device__ __forceinline__ float halve2(float a, float b, bool upper)
 template <int CTRL>
 __device__ __forceinline__ float fold1(float a) { return a + dpp_partner<CTRL>(a); }
 
+// The first two exchanges pair whole 4-lane banks of a row (lanes 0-7 with
+// 8-15, then 0-3 with 4-7 and 8-11 with 12-15), so each halving is two DPP
+// adds whose bank masks write the lower and the upper half of the pair into
+// the same register: no selects.  Written as one block: the only VALU-to-DPP
+// dependences inside it are at least four instructions apart, and the
+// leading and trailing s_nop 1 cover the producers before it and the DPP
+// reads after it.
 __device__ __forceinline__ float row_reduce10(const float v[10], int lane)
 {
-    const bool u8 = lane & 8, u4 = lane & 4, u2 = lane & 2, u1 = lane & 1;
-    const float a0 = halve2<kDppRor8>(v[0], v[1], u8);
-    const float a1 = halve2<kDppRor8>(v[2], v[3], u8);
-    const float a2 = halve2<kDppRor8>(v[4], v[5], u8);
-    const float a3 = halve2<kDppRor8>(v[6], v[7], u8);
-    const float a4 = halve2<kDppRor8>(v[8], v[9], u8);
-    const float b0 = halve2<kDppHalfMirror>(a0, a1, u4);
-    const float b1 = halve2<kDppHalfMirror>(a2, a3, u4);
-    const float b2 = fold1<kDppHalfMirror>(a4);
+    const bool u2 = lane & 2, u1 = lane & 1;
+    float a0, a1, a2, a3, a4, b0, b1, b2;
+    asm("s_nop 1\n\t"
+        "v_add_f32_dpp %0, %8, %8 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %0, %9, %9 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %1, %10, %10 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %1, %11, %11 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %2, %12, %12 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %2, %13, %13 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %3, %14, %14 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %3, %15, %15 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %4, %16, %16 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %4, %17, %17 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %5, %0, %0 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+        "v_add_f32_dpp %5, %1, %1 row_half_mirror row_mask:0xf bank_mask:0xa\n\t"
+        "v_add_f32_dpp %6, %2, %2 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+        "v_add_f32_dpp %6, %3, %3 row_half_mirror row_mask:0xf bank_mask:0xa\n\t"
+        "v_add_f32_dpp %7, %4, %4 row_half_mirror row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 1"
+        : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3), "=&v"(a4), "=&v"(b0), "=&v"(b1), "=&v"(b2)
+        : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]), "v"(v[8]),
+          "v"(v[9]));
     const float c0 = halve2<kDppXor2>(b0, b1, u2);
     const float c1 = fold1<kDppXor2>(b2);
     return halve2<kDppXor1>(c0, c1, u1);
