@@ -27,6 +27,16 @@ struct alignas(16) ViewDesc {
 };
 static_assert(sizeof(ViewDesc) == 128, "ViewDesc layout");
 
+// The view table is written before the kernels that read it and stays
+// unchanged while they run.  Read through the constant address space, a view
+// picked by a wave-uniform index is fetched with scalar loads into SGPRs,
+// instead of vector loads that the compiler must wait for at every view.
+typedef const __attribute__((address_space(4))) ViewDesc ConstViewDesc;
+__device__ __forceinline__ ConstViewDesc &const_view(const ViewDesc *views, int32_t v)
+{
+    return ((ConstViewDesc *)views)[v];
+}
+
 // Header at the start of `projected`.
 struct ProjHeader {
     int64_t counts[2];     // visible records, pairs

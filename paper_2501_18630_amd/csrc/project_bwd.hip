@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp,
         any = true;
         go += gbv.y;
         gb += gbv.z;
-        const ViewDesc &V = P.views[v];
+        ConstViewDesc &V = const_view(P.views, v);
         const double W[9] = {V.R[0], V.R[1], V.R[2], V.R[3], V.R[4], V.R[5], V.R[6], V.R[7], V.R[8]};
         const double tx = W[0] * mu[0] + W[1] * mu[1] + W[2] * mu[2] + (double)V.t[0];
         const double ty = W[3] * mu[0] + W[4] * mu[1] + W[5] * mu[2] + (double)V.t[1];
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
         any = true;
         for (int c = 0; c < 3; ++c) gc0[c] += gcf[c];
         if (M == 0) continue;
-        const ViewDesc &V = P.views[v];
+        ConstViewDesc &V = const_view(P.views, v);
         double vd3[3];
         for (int k = 0; k < 3; ++k)
             vd3[k] = mu[k] + ((double)V.R[k] * V.t[0] + (double)V.R[3 + k] * V.t[1] + (double)V.R[6 + k] * V.t[2]);
