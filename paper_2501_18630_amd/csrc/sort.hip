@@ -210,10 +210,12 @@ __device__ inline uint64_t match_digit(uint32_t d, bool valid)
 // Block b sorts elements [b * kSortTile, (b + 1) * kSortTile); inside it wave w
 // owns the contiguous 1024 elements from w * 1024, item k of lane l being
 // element w * 1024 + k * 64 + l, so that (wave, item, lane) is element order.
-// Digit counts are kept per wavefront in LDS and updated by one leader lane
-// per distinct digit with a plain read-add-write: the leaders of one wave
-// hold distinct digits, and no other wave touches the wave's row.  (LDS
-// float/int atomics serialise lanes; these updates are conflict-free.)
+// Digit counts are kept per wavefront in LDS.  The upsweep only counts, and
+// adds with LDS atomics (one instruction per item, no cross-lane matching).
+// The downsweep needs each element's rank among equal digits in element
+// order, so it matches digits across the wave and one leader lane per
+// distinct digit updates the count with a plain read-add-write: the leaders
+// of one wave hold distinct digits, and no other wave touches the wave's row.
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD
 // b % 8) and every XCD has its own L2.  Chunk c of the keys is given to
 // workgroup b with c = (b % 8) * (nb / 8) + b / 8 (up to the last nb % 8), so
@@ -256,13 +258,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
             const int64_t e = sort_elem(base, w, k, lane);
             d[k] = e < n ? (keys[e] >> shift) & dmask : RADIX;
         }
-        const uint64_t lt = lanemask_lt();
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {
-            const bool valid = d[k] < RADIX;
-            const uint64_t peers = match_digit<RB>(d[k], valid);
-            if (valid && (peers & lt) == 0) s_cnt[w][d[k]] += (uint32_t)__popcll(peers);
-        }
+        for (int k = 0; k < kSortItems; ++k)
+            if (d[k] < RADIX) atomicAdd(&s_cnt[w][d[k]], 1u);
     }
     __syncthreads();
 #pragma unroll
