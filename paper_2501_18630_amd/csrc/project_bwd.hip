@@ -65,16 +65,29 @@ __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp,
     bool any = false;
 
     // Lines of records the raster pass never touched (culled, or no pixel
-    // reached) are zero.  Each view's line is loaded one view ahead so that
-    // its latency overlaps the previous view's arithmetic.
-    float4 na = P.sgrad[4 * i], nb = P.sgrad[4 * i + 1];
+    // reached) are zero; those of culled records are not even read (the
+    // preprocess's visibility bits).  Each view's line is loaded one view ahead
+    // so that its latency overlaps the previous view's arithmetic.
+    uint64_t vm = P.vismask[i];
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 na = z4, nb = z4;
+    if (vm & 1u) {
+        na = P.sgrad[4 * i];
+        nb = P.sgrad[4 * i + 1];
+    }
     for (int32_t v = 0; v < n_views; ++v) {
         const float4 ga = na, gbv = nb;
+        const bool vis = (vm >> (v & 63)) & 1u;
+        na = nb = z4;
         if (v + 1 < n_views) {
-            const float4 *nl = P.sgrad + 4 * ((int64_t)(v + 1) * n + i);
-            na = nl[0];
-            nb = nl[1];
+            if (((v + 1) & 63) == 0) vm = P.vismask[(int64_t)((v + 1) >> 6) * n + i];
+            if ((vm >> ((v + 1) & 63)) & 1u) {
+                const float4 *nl = P.sgrad + 4 * ((int64_t)(v + 1) * n + i);
+                na = nl[0];
+                nb = nl[1];
+            }
         }
+        if (!vis) continue;
         // ga = (dmu'x, dmu'y, G00, G01), gbv = (G11, do, db, -)
         if (ga.x == 0.f && ga.y == 0.f && ga.z == 0.f && ga.w == 0.f && gbv.x == 0.f && gbv.y == 0.f &&
             gbv.z == 0.f)
@@ -186,8 +199,34 @@ __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp,
 // sin/cos, V normalised in FP64): near alignment 1 - d, dd/dtheta, dd/dphi and
 // the component of the lobe pull orthogonal to V are all O(angle) or smaller,
 // and FP32 directions carry ~1e-7 absolute error that swamps them (log d, and
-// with it dL/db_m, loses all relative accuracy as d -> 1).  ln d is taken from
-// whichever of d and d - 1 is exact, then the powers run in FP32.
+// with it dL/db_m, loses all relative accuracy as d -> 1).  log2 d is taken
+// from whichever of d and d - 1 is exact (lobe_log2), then the powers run in
+// FP32 on the hardware exp2.
+// log2 d for a lobe factor d in (0, 1], to FP32 relative precision.  Below
+// 1/2 the hardware log2 is well conditioned.  From 1/2 up, x = d - 1 is exact
+// in FP64 and ln d = log1p x = 2 atanh u with u = x / (2 + x), |u| <= 1/3:
+// the odd series of atanh in u^2 loses a factor 9 per term, seven terms
+// leave < 2e-8.  Both are evaluated and one is selected (no divergence).
+__device__ __forceinline__ float lobe_log2(double d)
+{
+    constexpr float kLog2e = 1.44269504088896341f;
+    const float lo = __builtin_amdgcn_logf(fmaxf((float)d, 1e-30f));
+    const float x = (float)(d - 1.0);
+    const float den = 2.0f + x;
+    float u = x * __builtin_amdgcn_rcpf(den);
+    u = __fmaf_rn(__fmaf_rn(-u, den, x), __builtin_amdgcn_rcpf(den), u);  // one Newton step
+    const float u2 = u * u;
+    float sr = 1.0f / 13.0f;
+    sr = __fmaf_rn(sr, u2, 1.0f / 11.0f);
+    sr = __fmaf_rn(sr, u2, 1.0f / 9.0f);
+    sr = __fmaf_rn(sr, u2, 1.0f / 7.0f);
+    sr = __fmaf_rn(sr, u2, 1.0f / 5.0f);
+    sr = __fmaf_rn(sr, u2, 1.0f / 3.0f);
+    sr = __fmaf_rn(sr, u2, 1.0f);
+    const float hi = 2.0f * kLog2e * u * sr;
+    return d < 0.5 ? lo : hi;
+}
+
 template <int M>
 __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
                                                                 GradPtrs g)
@@ -215,18 +254,30 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
         gcm[m][0] = gcm[m][1] = gcm[m][2] = 0.0f;
     }
     bool any = false;
-    // one view ahead, as in the geometry kernel
-    float4 na = P.sgrad[4 * i], nb = P.sgrad[4 * i + 1], nc = P.sgrad[4 * i + 2];
+    // one view ahead and visible records only, as in the geometry kernel
+    uint64_t vm = P.vismask[i];
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 na = z4, nb = z4, nc = z4;
+    if (vm & 1u) {
+        na = P.sgrad[4 * i];
+        nb = P.sgrad[4 * i + 1];
+        nc = P.sgrad[4 * i + 2];
+    }
     for (int32_t v = 0; v < n_views; ++v) {
         float4 *line = P.sgrad + 4 * ((int64_t)v * n + i);
         const float4 ga = na, gbv = nb, gcv = nc;
+        const bool vis = (vm >> (v & 63)) & 1u;
+        na = nb = nc = z4;
         if (v + 1 < n_views) {
-            const float4 *nl = line + 4 * n;
-            na = nl[0];
-            nb = nl[1];
-            nc = nl[2];
+            if (((v + 1) & 63) == 0) vm = P.vismask[(int64_t)((v + 1) >> 6) * n + i];
+            if ((vm >> ((v + 1) & 63)) & 1u) {
+                const float4 *nl = line + 4 * n;
+                na = nl[0];
+                nb = nl[1];
+                nc = nl[2];
+            }
         }
-        if (line_is_zero(ga, gbv, gcv)) continue;
+        if (!vis || line_is_zero(ga, gbv, gcv)) continue;
         {
             const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
             line[0] = z; line[1] = z; line[2] = z; line[3] = z;
@@ -248,8 +299,9 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
             const double lr0 = st[m] * cph[m], lr1 = st[m] * sph[m], lr2 = ct[m];
             const double d = lr0 * Vd[0] + lr1 * Vd[1] + lr2 * Vd[2];
             if (d > 0.0) {
-                const float lnd = d < 0.5 ? logf((float)d) : log1pf((float)(d - 1.0));
-                const float pw = expf((lbeta[m] - 1.0f) * lnd);             // d^(beta-1)
+                const float l2 = lobe_log2(d);
+                const float lnd = l2 * 0.69314718055994531f;
+                const float pw = __builtin_amdgcn_exp2f((lbeta[m] - 1.0f) * l2);  // d^(beta-1)
                 const float wgt = pw * (float)d;                             // d^beta
                 const float adj_w = gcf[0] * lcol[m][0] + gcf[1] * lcol[m][1] + gcf[2] * lcol[m][2];
                 for (int c = 0; c < 3; ++c) gcm[m][c] += wgt * gcf[c];
