@@ -139,12 +139,15 @@ __device__ __forceinline__ void finish_persistent(const RasterArgs &a, uint32_t 
 // lane i of a row the pixel (i & 3, i >> 2) of its quadrant.
 //
 // Culling in two levels.  When a batch of splats is staged in LDS, the staging
-// thread computes, for every block, the minimum of r^2 over the block's
-// pixel-centre rectangle.  Each wavefront then compacts the splats that reach
-// its block and tests its four quadrants the same way for those.  A rectangle
-// whose minimum is at least 1 + 1e-4 cannot hold a pixel with r^2 < 1 (the FP32
-// rounding of the minimum is far below that margin), so the splat is left out
-// of that list.  Each row walks its own list; the four rows of a wavefront
+// thread tests every block's pixel-centre rectangle: exactly (the minimum of
+// r^2 over it, as for quadrants below) in the reverse pass, against the
+// axis-aligned box of the splat's r^2 < 1 ellipse (cheap, conservative) in the
+// forward pass, where staging is a larger share of the work.  Each wavefront
+// then compacts the splats that reach its block and tests its four quadrants
+// exactly: the minimum of r^2 over the quadrant's pixel-centre rectangle.  A
+// rectangle whose minimum is at least 1 + 1e-4 cannot hold a pixel with
+// r^2 < 1 (the FP32 rounding of the minimum is far below that margin), so the
+// splat is left out of that row's list.  Each row walks its own list; the four rows of a wavefront
 // step through their lists together.  The lists change which (pixel, splat)
 // pairs are evaluated, never a result.
 
@@ -201,7 +204,7 @@ struct Staged {
 };
 
 // Stage records [lo, lo + nb) of the pair list into LDS slot k = j - lo.
-template <int TW, int TH>
+template <int TW, int TH, bool BOX_BLOCKS>
 __device__ __forceinline__ void stage(const RasterArgs &a, uint32_t lo, int nb, double dox, double doy,
                                       const Staged &S, int tid)
 {
@@ -210,13 +213,35 @@ __device__ __forceinline__ void stage(const RasterArgs &a, uint32_t lo, int nb, 
         const uint32_t rec = a.pair_rec[lo + (uint32_t)k];
         const RasterRec r = a.rec[rec];
         const double cx = r.cx - dox, cy = r.cy - doy;
-        uint32_t mask = 0;
-        const float fcx = (float)cx, fcy = (float)cy, f00 = (float)r.a00, f01 = (float)r.a01, f11 = (float)r.a11;
+        uint32_t mask = (1u << G::NW) - 1u;
+        const double det = BOX_BLOCKS ? r.a00 * r.a11 - r.a01 * r.a01 : 0.0;
+        if (!BOX_BLOCKS) {
+            // exact: the minimum of r^2 over the block's pixel-centre rectangle
+            const float fcx = (float)cx, fcy = (float)cy, f00 = (float)r.a00, f01 = (float)r.a01,
+                        f11 = (float)r.a11;
+            mask = 0;
 #pragma unroll
-        for (int w = 0; w < G::NW; ++w) {
-            const float bx = (float)((w % G::BX) * 8), by = (float)((w / G::BX) * 8);
-            const float m = rect_min_r2(fcx, fcy, f00, f01, f11, bx + 0.5f, bx + 7.5f, by + 0.5f, by + 7.5f);
-            if (!(m >= 1.0001f)) mask |= 1u << w;
+            for (int w = 0; w < G::NW; ++w) {
+                const float bx = (float)((w % G::BX) * 8), by = (float)((w / G::BX) * 8);
+                const float m = rect_min_r2(fcx, fcy, f00, f01, f11, bx + 0.5f, bx + 7.5f, by + 0.5f, by + 7.5f);
+                if (!(m >= 1.0001f)) mask |= 1u << w;
+            }
+        } else if (det > 0.0) {
+            // the axis-aligned box of the r^2 < 1 ellipse, half extents
+            // sqrt(Sigma'_xx) = sqrt(A11 / det A) and sqrt(Sigma'_yy), det A in FP64
+            // (no cancellation for elongated splats), widened by a relative 1e-4;
+            // det A <= 0 (not from a valid projection) keeps every block
+            const float fcx = (float)cx, fcy = (float)cy;
+            const float idet = __builtin_amdgcn_rcpf((float)det);
+            const float ex = __builtin_amdgcn_sqrtf((float)r.a11 * idet) * 1.0001f + 1e-4f;
+            const float ey = __builtin_amdgcn_sqrtf((float)r.a00 * idet) * 1.0001f + 1e-4f;
+            mask = 0;
+#pragma unroll
+            for (int w = 0; w < G::NW; ++w) {
+                const float bx = (float)((w % G::BX) * 8), by = (float)((w / G::BX) * 8);
+                if (fcx + ex >= bx + 0.5f && fcx - ex <= bx + 7.5f && fcy + ey >= by + 0.5f && fcy - ey <= by + 7.5f)
+                    mask |= 1u << w;
+            }
         }
         S.c[k] = make_double2(cx, cy);
         S.a[k] = make_double2(r.a00, 2.0 * r.a01);
@@ -337,7 +362,7 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
         for (uint32_t start = it.start; start < it.end; start += BATCH) {
             if (__syncthreads_count(!done) == 0) break;
             const int nb = (int)min((uint32_t)BATCH, it.end - start);
-            stage<TW, TH>(a, start, nb, (double)it.ox, (double)it.oy, S, tid);
+            stage<TW, TH, true>(a, start, nb, (double)it.ox, (double)it.oy, S, tid);
             __syncthreads();
             // rows whose pixels have all stopped take no entries
             const uint64_t live = __ballot(!done);
@@ -463,7 +488,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
             for (int64_t hi = maxlast + 1; hi > (int64_t)it.start; hi -= BATCH) {
                 const int64_t lo = hi - BATCH > (int64_t)it.start ? hi - BATCH : (int64_t)it.start;
                 const int nb = (int)(hi - lo);
-                stage<TW, TH>(a, (uint32_t)lo, nb, (double)it.ox, (double)it.oy, S, tid);
+                stage<TW, TH, false>(a, (uint32_t)lo, nb, (double)it.ox, (double)it.oy, S, tid);
                 for (int idx = tid; idx < G::NW * BATCH * NG; idx += NT) (&s_g[0][0][0])[idx] = 0.0f;
                 __syncthreads();
                 // this wave only needs its own splats up to its last contributor
@@ -661,7 +686,7 @@ __global__ __launch_bounds__(TW *TH) void raster_wave_stats_kernel(RasterArgs a,
     for (int64_t hi = maxlast + 1; hi > (int64_t)rg.x; hi -= BATCH) {
         const int64_t lo = hi - BATCH > (int64_t)rg.x ? hi - BATCH : (int64_t)rg.x;
         const int nb = (int)(hi - lo);
-        stage<TW, TH>(a, (uint32_t)lo, nb, (double)ox, (double)oy, S, tid);
+        stage<TW, TH, false>(a, (uint32_t)lo, nb, (double)ox, (double)oy, S, tid);
         __syncthreads();
         const int64_t kmax64 = (int64_t)wave_last - lo;
         const int nbw = kmax64 < (int64_t)(nb - 1) ? (int)kmax64 + 1 : nb;
