@@ -429,7 +429,10 @@ __device__ __forceinline__ void row_max4_i32(int v, int out[4])
 }
 
 template <int TW, int TH, int BATCH>
-__global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
+// At most 128 VGPRs below 512 threads (4 waves per SIMD, as many as the LDS
+// allows): the register allocator otherwise drifts past 128 on small source
+// changes.  32x16 tiles are held to 3 waves by their LDS anyway.
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH >= 512 ? 3 : 4))) void raster_bwd_kernel(RasterArgs a)
 {
     using G = Geo<TW, TH>;
     constexpr int NT = G::NT;
@@ -438,7 +441,7 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
     __shared__ double2 s_c[BATCH], s_a[BATCH], s_b[BATCH];
     __shared__ float4 s_col[BATCH];
     __shared__ uint32_t s_rec[BATCH];
-    __shared__ float s_g[G::NW][BATCH][NG];  // per-wave sums; wave 0's slot ends up with the total
+    __shared__ __align__(16) float s_g[G::NW][BATCH][NG];  // per-wave sums; wave 0's slot ends up with the total
     __shared__ uint8_t s_blist[G::NW][BATCH];
     __shared__ uint8_t s_rows[G::NW][4 * BATCH];
     __shared__ uint16_t s_share[G::NW][BATCH];
@@ -489,7 +492,9 @@ __global__ __launch_bounds__(TW *TH) void raster_bwd_kernel(RasterArgs a)
                 const int64_t lo = hi - BATCH > (int64_t)it.start ? hi - BATCH : (int64_t)it.start;
                 const int nb = (int)(hi - lo);
                 stage<TW, TH, false>(a, (uint32_t)lo, nb, (double)it.ox, (double)it.oy, S, tid);
-                for (int idx = tid; idx < G::NW * BATCH * NG; idx += NT) (&s_g[0][0][0])[idx] = 0.0f;
+                static_assert((G::NW * BATCH * NG) % 4 == 0, "slots are cleared in float4s");
+                for (int idx = tid; idx < G::NW * BATCH * NG / 4; idx += NT)
+                    reinterpret_cast<float4 *>(&s_g[0][0][0])[idx] = make_float4(0.f, 0.f, 0.f, 0.f);
                 __syncthreads();
                 // this wave only needs its own splats up to its last contributor
                 const int64_t kmax64 = (int64_t)wave_last - lo;
