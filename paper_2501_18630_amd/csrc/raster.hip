@@ -502,7 +502,8 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                 const int cnt_b = nbw > 0 ? build_list(s_col, nbw, w, s_blist[w], lane) : 0;
                 int cnt[4];
                 build_rows<BATCH>(S, s_blist[w], cnt_b, P.bx, P.by, lo, row_last, s_rows[w], cnt, lane);
-                const int my_cnt = pick4(cnt, P.row), steps = max4(cnt);
+                // wave-uniform (ballot counts): a scalar loop bound and counter
+                const int my_cnt = pick4(cnt, P.row), steps = __builtin_amdgcn_readfirstlane(max4(cnt));
                 mark_shared_steps<BATCH>(s_rows[w], cnt, steps, s_share[w], lane);
                 // list entries are read one step ahead
                 int kl_next = my_row[my_cnt > 0 ? my_cnt - 1 : 0];  // in bounds either way
