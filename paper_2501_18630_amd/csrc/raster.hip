@@ -499,6 +499,9 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                 // this wave only needs its own splats up to its last contributor
                 const int64_t kmax64 = (int64_t)wave_last - lo;
                 const int nbw = kmax64 < (int64_t)(nb - 1) ? (int)kmax64 + 1 : nb;
+                // this pixel's last contributor as a slot of the batch (-1: none in it)
+                const int64_t lk64 = (int64_t)last - lo;
+                const int last_k = lk64 < 0 ? -1 : (lk64 > (int64_t)BATCH ? BATCH : (int)lk64);
                 const int cnt_b = nbw > 0 ? build_list(s_col, nbw, w, s_blist[w], lane) : 0;
                 int cnt[4];
                 build_rows<BATCH>(S, s_blist[w], cnt_b, P.bx, P.by, lo, row_last, s_rows[w], cnt, lane);
@@ -512,7 +515,6 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                     const bool has = t >= 0;
                     const int k = has ? kl_next : 0;
                     kl_next = my_row[t > 0 ? t - 1 : 0];
-                    const int32_t j = (int32_t)(lo + k);
                     const bool owner = fld >= 0 && has;
                     float *dst = &s_g[w][k][fld < 0 ? 0 : fld];
                     // read early: the slot's running sum, added to at the end of the step
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                     const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
                     const double dxd = fpx - c.x, dyd = fpy - c.y;
                     const double r2 = eval_r2(dxd, dyd, aa.x, aa.y, bb.x);
-                    const bool contrib = has && j <= last && r2 < 1.0;
+                    const bool contrib = has && k <= last_k && r2 < 1.0;
                     if (!__ballot(contrib)) continue;
                     // Branch-free from here: a lane that does not take part uses
                     // r^2 = 0 (finite logs) and alpha = 0 (T, S unchanged), and
