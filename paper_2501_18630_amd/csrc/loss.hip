@@ -16,7 +16,9 @@
 // the 42 x 26 partials region, 5 more for their window sums), separable
 // window passes (row then column, the 2D window being g(a) g(b)), the SSIM
 // map and its partials, their window sums and the gradient, which is written
-// once.  HBM traffic is 12 bytes per channel-pixel.
+// once.  The partials reuse the input region's LDS (x and y of the output
+// pixels are read again from memory, a cache hit), so three workgroups fit
+// on a CU instead of two.  HBM traffic is 12 bytes per channel-pixel.
 #include "dbs_internal.h"
 
 namespace dbs {
@@ -47,9 +49,13 @@ __global__ __launch_bounds__(256) void photometric_loss_kernel(LossViews lv, con
                                                                const float *__restrict__ target, float lam,
                                                                float *__restrict__ grad, float *loss)
 {
-    __shared__ float s_x[kIY][kIX], s_y[kIY][kIX];
+    // the input region is only needed for the row sums: the partials reuse its space
+    constexpr int kXYD = 2 * kIY * kIX > 3 * kMY * kMX ? 2 * kIY * kIX : 3 * kMY * kMX;
+    __shared__ float s_xyd[kXYD];
     __shared__ float s_h[5][kIY][kMX];   // row sums of x, y, xx, yy, xy; later the row sums of the partials
-    __shared__ float s_d[3][kMY][kMX];   // dS/dm1, dS/de11, dS/de12
+    float(*s_x)[kIX] = reinterpret_cast<float(*)[kIX]>(s_xyd);
+    float(*s_y)[kIX] = reinterpret_cast<float(*)[kIX]>(s_xyd + kIY * kIX);
+    float(*s_d)[kMY][kMX] = reinterpret_cast<float(*)[kMY][kMX]>(s_xyd);  // dS/dm1, dS/de11, dS/de12
     __shared__ float s_red[2][256 / kWave];
     const int tid = threadIdx.x;
     const int item = blockIdx.x;
@@ -194,7 +200,8 @@ __global__ __launch_bounds__(256) void photometric_loss_kernel(LossViews lv, con
                     w2 = fmaf(g[k], bv[1][j + k], w2);
                     w3 = fmaf(g[k], bv[2][j + k], w3);
                 }
-                const float x = s_x[r + 2 * kR][q + 2 * kR], y = s_y[r + 2 * kR][q + 2 * kR];
+                const int64_t o = (int64_t)gy * V.w + gx;
+                const float x = xs[o], y = ys[o];
                 const float d = x - y;
                 const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
                 l1_sum += fabsf(d);
