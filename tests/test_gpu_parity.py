@@ -210,16 +210,23 @@ def _dl(cams, seed):
     return [rng.standard_normal((3, c["height"], c["width"])).astype(np.float32) for c in cams]
 
 
-@pytest.mark.parametrize("which", ["tiny", "c0", "multiview"])
+@pytest.mark.parametrize("which", ["tiny", "c0", "multiview", "70views"])
 def test_backward_matches_oracle(oracle, which):
     if which == "c0":
         s, cams = scenes.config0()
     elif which == "tiny":
         s, cams = tiny_scene(60, 13, m=2), [scenes.look_at_camera([1.0, 0.5, -5.0], 40, 30,
                                                                   background=(0.3, 0.2, 0.1))]
-    else:
+    elif which == "multiview":
         s = tiny_scene(120, 17, m=4)
         cams = [scenes.look_at_camera(p, 36, 28) for p in ([0, 0, -6.0], [2.5, -1.0, -5.0], [-3.0, 1.0, -4.0])]
+    else:
+        # more views than one 64-bit word of per-splat visibility bits holds,
+        # each seeing a different part of the scene
+        s = tiny_scene(80, 19, m=2)
+        ang = np.linspace(0.0, 2.0 * np.pi, 70, endpoint=False)
+        cams = [scenes.look_at_camera([5.0 * np.sin(a), 0.7 * np.cos(3 * a), -5.0 * np.cos(a)], 20, 14)
+                for a in ang]
     dl = _dl(cams, 42)
     out = gpu_render(s, cams, grads_from=dl)
     g_ref = {k: 0.0 for k in PARAMS}
