@@ -183,6 +183,18 @@ def work_counts(rast, step):
     return counts
 
 
+def atomic_count(rast, step):
+    """Global float atomics one raster reverse pass issues (one per non-zero
+    (tile, splat, value) sum), from the counting build on the step's last
+    state; the projection reverse that follows clears the accumulator again.
+    Outside the timed region."""
+    import torch
+    cnt = torch.zeros(1, dtype=torch.int64, device=rast.device)
+    rast.raster_bwd(step.dL, step.final_T, step.last, atomics=cnt)
+    rast.project_bwd(step.params, step.grads)
+    return int(cnt.item())
+
+
 def cpu_baseline(scene, cams, n_pixels: int, seed: int = 5):
     """The oracle, as it is, on a bounded sample: fwd + bwd of `n_pixels`
     random pixels of the first view (every splat of the scene is projected
@@ -277,6 +289,8 @@ def main():
     log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in st.items()))
     wc = work_counts(rast, step)
     log(f"work: {wc}")
+    n_atomics = atomic_count(rast, step)
+    log(f"raster reverse: {n_atomics} global float atomics per pass")
     t_photo, t_reg = composite_loss_times(rast, step, max(3, args.steps // 2))
     log(f"composite loss (ms): photometric {t_photo:.3f}, regularisers {t_reg:.3f}")
     t_reloc, t_noise, n_moved = mcmc_times(params, n, m, 3)
@@ -326,6 +340,9 @@ def main():
         # not in the step: the MCMC step of Sec. 3.4 over all splats (dead: o <= 0.005)
         "mcmc": {"relocate_ms": round(t_reloc, 4), "noise_ms": round(t_noise, 4), "relocated": n_moved},
         "work": wc,
+        "global_atomics": {"per_raster_bwd": n_atomics,
+                           "per_s": round(n_atomics / (st["raster_bwd"] * 1e-3), 1),
+                           "bytes_added": 4 * n_atomics},
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene, cams, args.cpu_sample_pixels)

@@ -306,6 +306,16 @@ dbs_status dbs_mcmc_noise(const dbs_splats_mut *splats /*[host] struct of device
 
 /* ---- introspection (tests, profiling) ------------------------------------ */
 
+/* dbs_raster_bwd that also ADDS the number of global float atomics it issues
+ * (one per non-zero (tile, splat, value) sum sent to the accumulator) to
+ * *atomics (device int64), for atomic-throughput measurement.  Same
+ * arguments and effect as dbs_raster_bwd otherwise; a separate, slightly
+ * slower kernel build.  DBS_ERR_INVALID_ARGUMENT if atomics is NULL. */
+dbs_status dbs_raster_bwd_count(const void *projected, const void *bins, const dbs_camera *cams /*[host]*/,
+                                int32_t n_views, const dbs_raster_cfg *cfg /*[host]*/, int64_t n,
+                                const float *final_T, const int32_t *last_index, const float *dL_dimage,
+                                int64_t *atomics /*[device]*/, void *stream);
+
 /* Device pointers into `projected` for n splats and n_views views:
  * per record r = v n + i (view-major):
  *   record [R] 64-byte line: double cx, cy (mu' in pixels); double A00, A01,

@@ -28,7 +28,7 @@ EXPORTS = ("dbs_default_cfg", "dbs_projected_bytes", "dbs_bins_bytes", "dbs_work
            "dbs_preprocess", "dbs_bin_sort", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
            "dbs_photometric_loss", "dbs_regularizer", "dbs_mcmc_workspace_bytes", "dbs_mcmc_relocate",
            "dbs_mcmc_noise",
-           "dbs_raster_bwd", "dbs_project_bwd", "dbs_render_stats",
+           "dbs_raster_bwd", "dbs_raster_bwd_count", "dbs_project_bwd", "dbs_render_stats",
            "dbs_projected_layout", "dbs_bins_layout", "dbs_status_string", "dbs_version")
 
 
@@ -75,6 +75,7 @@ def _declare(lib):
     lib.dbs_render_fwd.argtypes = [P, P, P, I32, P, I64, P, P, P, P]
     lib.dbs_render_bwd.argtypes = [P, P, P, P, I32, P, P, P, P, P, P]
     lib.dbs_raster_bwd.argtypes = [P, P, P, I32, P, I64, P, P, P, P]
+    lib.dbs_raster_bwd_count.argtypes = [P, P, P, I32, P, I64, P, P, P, P, P]
     lib.dbs_project_bwd.argtypes = [P, P, P, I32, P, P, P]
     lib.dbs_render_stats.argtypes = [P, P, P, I32, P, I64, P, P, P, P]
     lib.dbs_l1_loss.argtypes = [P, P, I64, C.c_float, P, P, P]
@@ -88,7 +89,7 @@ def _declare(lib):
     lib.dbs_bins_layout.argtypes = [P, I64, P, I32, P] + [C.POINTER(C.c_void_p)] * 3 + [C.POINTER(C.c_int64)]
     for f in ("dbs_preprocess", "dbs_bin_sort", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
               "dbs_photometric_loss", "dbs_regularizer", "dbs_mcmc_workspace_bytes", "dbs_mcmc_relocate",
-           "dbs_mcmc_noise", "dbs_raster_bwd", "dbs_project_bwd", "dbs_render_stats",
+           "dbs_mcmc_noise", "dbs_raster_bwd", "dbs_raster_bwd_count", "dbs_project_bwd", "dbs_render_stats",
               "dbs_projected_layout", "dbs_bins_layout"):
         getattr(lib, f).restype = C.c_int
     lib.dbs_status_string.argtypes = [C.c_int]

@@ -191,9 +191,9 @@ static dbs_status check_grads(const dbs_splats *splats, const dbs_splat_grads *g
     return DBS_OK;
 }
 
-dbs_status dbs_raster_bwd(const void *projected, const void *bins, const dbs_camera *cams, int32_t n_views,
-                          const dbs_raster_cfg *cfg, int64_t n, const float *final_T, const int32_t *last_index,
-                          const float *dL_dimage, void *stream)
+static dbs_status raster_bwd(const void *projected, const void *bins, const dbs_camera *cams, int32_t n_views,
+                             const dbs_raster_cfg *cfg, int64_t n, const float *final_T, const int32_t *last_index,
+                             const float *dL_dimage, int64_t *atomics, void *stream)
 {
     DBS_TRY(check_cams(cams, n_views));
     DBS_TRY(check_cfg(cfg));
@@ -204,7 +204,22 @@ dbs_status dbs_raster_bwd(const void *projected, const void *bins, const dbs_cam
     ProjPtrs P = proj_ptrs((void *)projected, n, n_views);
     BinsPtrs B = bins_ptrs((void *)bins, n_tiles);
     return hip_status(launch_raster_bwd(P, B, n, n_views, n_tiles, *cfg, final_T, last_index, dL_dimage,
-                                        (float *)P.sgrad, (hipStream_t)stream));
+                                        (float *)P.sgrad, atomics, (hipStream_t)stream));
+}
+
+dbs_status dbs_raster_bwd(const void *projected, const void *bins, const dbs_camera *cams, int32_t n_views,
+                          const dbs_raster_cfg *cfg, int64_t n, const float *final_T, const int32_t *last_index,
+                          const float *dL_dimage, void *stream)
+{
+    return raster_bwd(projected, bins, cams, n_views, cfg, n, final_T, last_index, dL_dimage, nullptr, stream);
+}
+
+dbs_status dbs_raster_bwd_count(const void *projected, const void *bins, const dbs_camera *cams, int32_t n_views,
+                                const dbs_raster_cfg *cfg, int64_t n, const float *final_T,
+                                const int32_t *last_index, const float *dL_dimage, int64_t *atomics, void *stream)
+{
+    if (!atomics) return DBS_ERR_INVALID_ARGUMENT;
+    return raster_bwd(projected, bins, cams, n_views, cfg, n, final_T, last_index, dL_dimage, atomics, stream);
 }
 
 dbs_status dbs_project_bwd(const dbs_splats *splats, const void *projected, const dbs_camera *cams, int32_t n_views,

@@ -240,7 +240,7 @@ hipError_t launch_raster_fwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
                              int32_t *last_index, hipStream_t s);
 hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views, int64_t n_tiles,
                              const dbs_raster_cfg &cfg, const float *final_T,
-                             const int32_t *last_index, const float *dL_dimage, float *sgrad,
+                             const int32_t *last_index, const float *dL_dimage, float *sgrad, int64_t *atomics,
                              hipStream_t s);
 hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t n_tiles,
                                const dbs_raster_cfg &cfg, const float *final_T, const int32_t *last_index,

@@ -55,6 +55,7 @@ struct RasterArgs {
     float *sgrad;     // [R][16] screen-space gradient per record
     float t_eps, alpha_max;
     int32_t persistent;
+    unsigned long long *atomics;  // counting reverse pass only: global float atomics issued (added to)
 };
 
 // r^2 = A00 dx^2 + 2 A01 dx dy + A11 dy^2 in FP64 with a fixed rounding
@@ -412,6 +413,14 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
 
 // ---------------------------------------------------------------- reverse
 
+__device__ __forceinline__ uint64_t wave_sum_u32(uint32_t v)
+{
+    uint64_t x = v;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
+}
+
 __device__ __forceinline__ int wave_max_i32(int v)
 {
 #pragma unroll
@@ -428,10 +437,11 @@ __device__ __forceinline__ void row_max4_i32(int v, int out[4])
     for (int r = 0; r < 4; ++r) out[r] = __builtin_amdgcn_readlane(v, 16 * r);
 }
 
-template <int TW, int TH, int BATCH>
 // At most 128 VGPRs below 512 threads (4 waves per SIMD, as many as the LDS
 // allows): the register allocator otherwise drifts past 128 on small source
-// changes.  32x16 tiles are held to 3 waves by their LDS anyway.
+// changes.  32x16 tiles are held to 3 waves by their LDS anyway.  COUNT: the
+// introspection variant that also counts the global float atomics it issues.
+template <int TW, int TH, int BATCH, bool COUNT = false>
 __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH >= 512 ? 3 : 4))) void raster_bwd_kernel(RasterArgs a)
 {
     using G = Geo<TW, TH>;
@@ -454,6 +464,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
     const uint8_t *my_row = &s_rows[w][P.row * BATCH];
     const float kLn2 = 0.69314718055994531f;
     const int fld = row10_field(lane);  // value whose row total this lane stores
+    uint32_t n_atomics = 0;  // COUNT only
 
     for (int iter = 0;; ++iter) {
         if (!fetch_item<TW, TH>(a, &a.queue[2], &s_item, iter)) break;
@@ -603,11 +614,16 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                     const int k = idx / NG, f = idx - k * NG;
                     const float sg = s_g[0][k][f];
                     if (sg != 0.0f) unsafeAtomicAdd(&a.sgrad[(int64_t)s_rec[k] * 16 + f], sg);
+                    if (COUNT) n_atomics += sg != 0.0f;
                 }
                 __syncthreads();
             }
         }
         __syncthreads();
+    }
+    if (COUNT) {
+        const uint64_t tot = wave_sum_u32(n_atomics);
+        if (lane == 0 && tot) atomicAdd(a.atomics, (unsigned long long)tot);
     }
     finish_persistent(a, &a.queue[2], &a.queue[3]);
 }
@@ -729,14 +745,15 @@ struct Kern {
     static constexpr int BWD_BATCH = BATCH < 128 ? BATCH : 128;
     static void *fwd() { return (void *)raster_fwd_kernel<TW, TH, BATCH>; }
     static void *bwd() { return (void *)raster_bwd_kernel<TW, TH, BWD_BATCH>; }
+    static void *bwd_count() { return (void *)raster_bwd_kernel<TW, TH, BWD_BATCH, true>; }
 };
 
 struct Entry {
     int tw, th, batch;
-    void *fwd, *bwd;
+    void *fwd, *bwd, *bwd_count;
 };
 
-#define DBS_ENTRY(TW, TH, B) {TW, TH, B, Kern<TW, TH, B>::fwd(), Kern<TW, TH, B>::bwd()}
+#define DBS_ENTRY(TW, TH, B) {TW, TH, B, Kern<TW, TH, B>::fwd(), Kern<TW, TH, B>::bwd(), Kern<TW, TH, B>::bwd_count()}
 const Entry kEntries[] = {
     DBS_ENTRY(16, 16, 64),  DBS_ENTRY(16, 16, 128), DBS_ENTRY(16, 16, 256),
     DBS_ENTRY(16, 8, 64),   DBS_ENTRY(16, 8, 128),  DBS_ENTRY(16, 8, 256),
@@ -829,7 +846,7 @@ hipError_t launch_raster_fwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
 
 hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views, int64_t n_tiles,
                              const dbs_raster_cfg &cfg, const float *final_T, const int32_t *last_index,
-                             const float *dL_dimage, float *sgrad, hipStream_t s)
+                             const float *dL_dimage, float *sgrad, int64_t *atomics, hipStream_t s)
 {
     (void)n;
     const Entry *e = find_entry(cfg.tile_w, cfg.tile_h, cfg.batch);
@@ -839,7 +856,8 @@ hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
     a.last_index = (int32_t *)last_index;
     a.dL_dimage = dL_dimage;
     a.sgrad = sgrad;
-    return launch(e->bwd, cfg.tile_w * cfg.tile_h, a, n_tiles, s);
+    a.atomics = (unsigned long long *)atomics;
+    return launch(atomics ? e->bwd_count : e->bwd, cfg.tile_w * cfg.tile_h, a, n_tiles, s);
 }
 
 bool raster_supported(int tw, int th, int batch) { return find_entry(tw, th, batch) != nullptr; }

@@ -161,11 +161,20 @@ class Rasterizer:
             self.cams_c, self.V, C.byref(self.cfg_c), C.c_void_p(final_T.data_ptr()),
             C.c_void_p(last.data_ptr()), C.c_void_p(dL_dimage.data_ptr()), C.byref(gr), _stream()))
 
-    def raster_bwd(self, dL_dimage, final_T, last):
-        check("dbs_raster_bwd", self.lib.dbs_raster_bwd(
-            C.c_void_p(self.projected.data_ptr()), C.c_void_p(self.bins.data_ptr()), self.cams_c, self.V,
-            C.byref(self.cfg_c), self.n, C.c_void_p(final_T.data_ptr()), C.c_void_p(last.data_ptr()),
-            C.c_void_p(dL_dimage.data_ptr()), _stream()))
+    def raster_bwd(self, dL_dimage, final_T, last, atomics=None):
+        """Raster reverse pass into the accumulator; with `atomics` (a device
+        int64 tensor) the counting build runs and adds the number of global
+        float atomics it issued."""
+        if atomics is None:
+            check("dbs_raster_bwd", self.lib.dbs_raster_bwd(
+                C.c_void_p(self.projected.data_ptr()), C.c_void_p(self.bins.data_ptr()), self.cams_c, self.V,
+                C.byref(self.cfg_c), self.n, C.c_void_p(final_T.data_ptr()), C.c_void_p(last.data_ptr()),
+                C.c_void_p(dL_dimage.data_ptr()), _stream()))
+        else:
+            check("dbs_raster_bwd_count", self.lib.dbs_raster_bwd_count(
+                C.c_void_p(self.projected.data_ptr()), C.c_void_p(self.bins.data_ptr()), self.cams_c, self.V,
+                C.byref(self.cfg_c), self.n, C.c_void_p(final_T.data_ptr()), C.c_void_p(last.data_ptr()),
+                C.c_void_p(dL_dimage.data_ptr()), C.c_void_p(atomics.data_ptr()), _stream()))
 
     def project_bwd(self, params: dict, grads: dict):
         sp = _splats_c(params, self.n, self.m)

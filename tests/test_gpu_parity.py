@@ -351,6 +351,28 @@ def test_backward_repeatable_split_and_work_counts(oracle):
     assert st["bwd_evaluated"] >= st["contributing"] and st["fwd_evaluated"] >= st["bwd_evaluated"]
 
 
+def test_counting_backward_matches_and_counts(oracle):
+    """The atomic-counting build of the raster reverse pass gives the same
+    gradients and counts at most one atomic per (tile, splat, value)."""
+    import torch
+    from paper_2501_18630_amd import renderer
+    s, cams = scenes.config0()
+    rast = renderer.Rasterizer(cams, 256, 2)
+    params = renderer.to_device(s)
+    img, T, last = rast.forward(params)
+    dl = torch.as_tensor(np.random.default_rng(7).standard_normal(img.numel()).astype(np.float32)).cuda()
+    runs, cnt = [], torch.zeros(1, dtype=torch.int64, device="cuda")
+    for counted in (False, True):
+        g = {k: torch.zeros_like(params[k]) for k in PARAMS}
+        rast.raster_bwd(dl, T, last, atomics=cnt if counted else None)
+        rast.project_bwd(params, g)
+        runs.append({k: v.cpu().numpy() for k, v in g.items()})
+    for k in PARAMS:
+        np.testing.assert_allclose(runs[1][k], runs[0][k], rtol=1e-5, atol=1e-9)
+    n_at = int(cnt.item())
+    assert 0 < n_at <= 10 * int(rast.counts[1].item())
+
+
 def test_l1_loss_glue():
     import torch
     from paper_2501_18630_amd import renderer
