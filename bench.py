@@ -219,8 +219,8 @@ def cpu_baseline(scene, cams, n_pixels: int, seed: int = 5):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU would shard views, see DESIGN.md)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
+                                   "(a multi-GPU run would shard the views across GPUs)"}))
         sys.exit(2)
     import torch
     from paper_2501_18630_amd import renderer, scenes

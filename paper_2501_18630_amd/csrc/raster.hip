@@ -146,9 +146,10 @@ __device__ __forceinline__ void finish_persistent(const RasterArgs &a, uint32_t 
 // forward pass, where staging is a larger share of the work.  Each wavefront
 // then compacts the splats that reach its block and tests its four quadrants
 // exactly: the minimum of r^2 over the quadrant's pixel-centre rectangle.  A
-// rectangle whose minimum is at least 1 + 1e-4 cannot hold a pixel with
-// r^2 < 1 (the FP32 rounding of the minimum is far below that margin), so the
-// splat is left out of that row's list.  Each row walks its own list; the four rows of a wavefront
+// rectangle whose minimum is at least 1 + 1e-4 (+ a term for elongated
+// splats, cull_threshold) cannot hold a pixel with r^2 < 1: the FP32 error of
+// the minimum is below that margin, so the splat is left out of that row's
+// list.  Each row walks its own list; the four rows of a wavefront
 // step through their lists together.  The lists change which (pixel, splat)
 // pairs are evaluated, never a result.
 
@@ -194,6 +195,24 @@ __device__ __forceinline__ float rect_min_r2(float cx, float cy, float a00, floa
     return best;
 }
 
+// Culling threshold for the FP32 minimum of r^2 over a rectangle.  Rounding
+// the conic to FP32 and evaluating the form perturb r^2 by a few ulp of the
+// unsigned form |A00| dx^2 + 2 |A01 dx dy| + |A11| dy^2, which is at most about
+// 2 kappa r^2 for the condition number kappa = l_max / l_min of A (the square
+// of the footprint's aspect ratio).  The threshold adds 1e-6 kappa (over 16
+// ulp of that) to the 1e-4 margin, so that no splat, however elongated, is
+// culled from a rectangle holding a pixel with r^2 < 1.  kappa =
+// (tr + sqrt(tr^2 - 4 det))^2 / (4 det), det in FP64.
+__device__ __forceinline__ float cull_threshold(double a00, double a01, double a11)
+{
+    const float fdet = (float)(a00 * a11 - a01 * a01);
+    if (!(fdet > 0.0f)) return 3.0e38f;  // not a valid projection: never cull
+    const float tr = (float)(a00 + a11);
+    const float r = __builtin_amdgcn_sqrtf(fmaxf(tr * tr - 4.0f * fdet, 0.0f));
+    const float kappa = (tr + r) * (tr + r) * __builtin_amdgcn_rcpf(4.0f * fdet);
+    return 1.0001f + 1e-6f * kappa;
+}
+
 // LDS image of a staged splat: tile-local centre and conic in FP64, (o, beta)
 // packed in the second half of s_b, colour and the block mask in s_col.
 struct Staged {
@@ -220,12 +239,13 @@ __device__ __forceinline__ void stage(const RasterArgs &a, uint32_t lo, int nb, 
             // exact: the minimum of r^2 over the block's pixel-centre rectangle
             const float fcx = (float)cx, fcy = (float)cy, f00 = (float)r.a00, f01 = (float)r.a01,
                         f11 = (float)r.a11;
+            const float thr = cull_threshold(r.a00, r.a01, r.a11);
             mask = 0;
 #pragma unroll
             for (int w = 0; w < G::NW; ++w) {
                 const float bx = (float)((w % G::BX) * 8), by = (float)((w / G::BX) * 8);
                 const float m = rect_min_r2(fcx, fcy, f00, f01, f11, bx + 0.5f, bx + 7.5f, by + 0.5f, by + 7.5f);
-                if (!(m >= 1.0001f)) mask |= 1u << w;
+                if (!(m >= thr)) mask |= 1u << w;
             }
         } else if (det > 0.0) {
             // the axis-aligned box of the r^2 < 1 ellipse, half extents
@@ -283,12 +303,13 @@ __device__ __forceinline__ void build_rows(const Staged &S, const uint8_t *blist
         const double2 c = S.c[k], aa = S.a[k], bb = S.b[k];
         const float fcx = (float)c.x, fcy = (float)c.y;
         const float f00 = (float)aa.x, f01 = (float)(0.5 * aa.y), f11 = (float)bb.x;
+        const float thr = cull_threshold(aa.x, 0.5 * aa.y, bb.x);
         const int32_t j = (int32_t)(lo + k);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float x0 = (float)(bx + (r & 1) * 4) + 0.5f, y0 = (float)(by + (r >> 1) * 4) + 0.5f;
             const bool in = valid && j <= lim[r] &&
-                            !(rect_min_r2(fcx, fcy, f00, f01, f11, x0, x0 + 3.0f, y0, y0 + 3.0f) >= 1.0001f);
+                            !(rect_min_r2(fcx, fcy, f00, f01, f11, x0, x0 + 3.0f, y0, y0 + 3.0f) >= thr);
             const uint64_t bal = __ballot(in);
             if (in) rows[r * BATCH + cnt[r] + __popcll(bal & lanes_below(lane))] = (uint8_t)k;
             cnt[r] += __popcll(bal);
