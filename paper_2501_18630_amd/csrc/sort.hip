@@ -238,18 +238,19 @@ template <int RB>
 __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint32_t *keys, Count cnt, int shift,
                                                                      int width, uint32_t *hist, int64_t nblocks)
 {
-    constexpr int NW = kSortThreads / kWave, RADIX = 1 << RB, DPT = RADIX / kSortThreads;
-    __shared__ uint32_t s_cnt[NW][RADIX];
+    // UC count rows per wave, lane l adding into row l % UC: equal digits of
+    // one wave then collide UC times less, and the odd row stride puts the
+    // rows' copies of one digit in different banks
+    constexpr int NW = kSortThreads / kWave, RADIX = 1 << RB, DPT = RADIX / kSortThreads, UC = 4;
+    constexpr int STRIDE = RADIX + 1, ROWS = NW * UC;
+    __shared__ uint32_t s_cnt[ROWS * STRIDE];
     const uint32_t dmask = (1u << width) - 1u;
     const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
     const int64_t n = cnt.get();
     const int64_t nb_used = (n + kSortTile - 1) / kSortTile;  // the grid is sized for the capacity
     const int64_t chunk = (int64_t)blockIdx.x < nb_used ? xcd_chunk(blockIdx.x, nb_used) : (int64_t)blockIdx.x;
     const int64_t base = chunk * kSortTile;
-#pragma unroll
-    for (int ww = 0; ww < NW; ++ww)
-#pragma unroll
-        for (int q = 0; q < DPT; ++q) s_cnt[ww][q * kSortThreads + t] = 0;
+    for (int i = t; i < ROWS * STRIDE; i += kSortThreads) s_cnt[i] = 0;
     __syncthreads();
     if (base < n) {
         uint32_t d[kSortItems];
@@ -258,9 +259,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
             const int64_t e = sort_elem(base, w, k, lane);
             d[k] = e < n ? (keys[e] >> shift) & dmask : RADIX;
         }
+        uint32_t *row = s_cnt + (w * UC + (lane & (UC - 1))) * STRIDE;
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k)
-            if (d[k] < RADIX) atomicAdd(&s_cnt[w][d[k]], 1u);
+            if (d[k] < RADIX) atomicAdd(&row[d[k]], 1u);
     }
     __syncthreads();
 #pragma unroll
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
         const int dd = q * kSortThreads + t;
         uint32_t tot = 0;
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) tot += s_cnt[ww][dd];
+        for (int r = 0; r < ROWS; ++r) tot += s_cnt[r * STRIDE + dd];
         hist[(int64_t)dd * nblocks + chunk] = tot;
     }
 }
