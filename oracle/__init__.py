@@ -13,7 +13,10 @@ Functions and the passage each follows:
   beta_kernel ...... Sec. 3.1, Eqs. (2)-(3)
   quat_to_rot ...... Sec. 3.2 (R from the quaternion q of Eq. 4)
   project .......... Sec. 3.2 (Sigma, Sigma' = J W Sigma W^T J^T, mu'), Sec. 3.3 Eq. (8)
-  render ........... Sec. 3.2, Eqs. (5)-(6)
+  render ........... Sec. 3.2, Eqs. (5)-(6); with scene["sh"] ([n, 16, 3]) the
+                     comparison mode: Gaussian kernel cut at 3 sigma and
+                     degree-3 SH colour (Sec. 3.3, Sec. 4), forward only
+  sh_basis3 ........ real spherical harmonics of degree <= 3
   render_bwd ....... exact reverse mode of `render`
   bin_pairs ........ tile binning + (depth, id) order of the splats overlapping each tile
 """
@@ -53,7 +56,7 @@ class _Camera(C.Structure):
 
 
 class _Splats(C.Structure):
-    _fields_ = [("n", C.c_int64), ("m", C.c_int32)] + [(k, C.c_void_p) for k in PARAMS]
+    _fields_ = [("n", C.c_int64), ("m", C.c_int32)] + [(k, C.c_void_p) for k in PARAMS] + [("sh", C.c_void_p)]
 
 
 class _Grads(C.Structure):
@@ -70,6 +73,7 @@ def _load():
         lib.ob_beta_kernel.restype = C.c_double
         lib.ob_beta_kernel.argtypes = [C.c_double, C.c_double]
         lib.ob_quat_to_rot.argtypes = [P, P]
+        lib.ob_sh_basis3.argtypes = [P, P]
         lib.ob_project.argtypes = [P, P] + [P] * 10
         lib.ob_render.argtypes = [P, P, C.c_double, C.c_double, C.c_int64, P, P, P, P, P, P]
         lib.ob_render_bwd.argtypes = [P, P, C.c_double, C.c_double, C.c_int64, P, P, P, P]
@@ -88,13 +92,15 @@ def _ptr(a: np.ndarray):
 
 
 def _scene64(scene: dict) -> dict:
-    return {k: np.ascontiguousarray(scene[k], dtype=np.float64) for k in PARAMS}
+    keys = PARAMS + (("sh",) if scene.get("sh") is not None else ())
+    return {k: np.ascontiguousarray(scene[k], dtype=np.float64) for k in keys}
 
 
 def _splats(s64: dict) -> _Splats:
     n = s64["means"].shape[0]
     m = s64["lobe_betas"].shape[1] if s64["lobe_betas"].ndim == 2 else 0
-    return _Splats(n, m, *[s64[k].ctypes.data for k in PARAMS])
+    sh = s64["sh"].ctypes.data if "sh" in s64 else None
+    return _Splats(n, m, *[s64[k].ctypes.data for k in PARAMS], sh)
 
 
 def _camera(cam: dict) -> _Camera:
@@ -109,6 +115,16 @@ def _camera(cam: dict) -> _Camera:
 def beta_kernel(x: float, b: float) -> float:
     """B(x; b) = (1 - x)^(4 e^b) on [0, 1], zero for x >= 1."""
     return _load().ob_beta_kernel(float(x), float(b))
+
+
+def sh_basis3(d) -> np.ndarray:
+    """The 16 real spherical harmonics of degree <= 3 at the unit direction d,
+    order (l, m) = (0, 0), (1, -1), (1, 0), (1, 1), ..., (3, 3), Condon-Shortley
+    phase."""
+    d = np.ascontiguousarray(d, np.float64).reshape(3)
+    Y = np.zeros(16)
+    _load().ob_sh_basis3(_ptr(d), _ptr(Y))
+    return Y
 
 
 def quat_to_rot(q) -> np.ndarray:

@@ -15,6 +15,8 @@
  *   r_i(x)^2 = (x - mu')^T Sigma'^{-1} (x - mu') ............ Sec. 3.2, Eq. (5)
  *   depth-ordered front-to-back compositing ................. Sec. 3.2, Eq. (6)
  *   Spherical Beta colour c0 + sum_m B(1 - R_m.V; b_m) c_m .. Sec. 3.3, Eq. (8)
+ *   comparison mode: Gaussian kernel + degree-3 SH colour ... Sec. 3.3 (the
+ *     spherical-harmonics colour it replaces), Sec. 4 (the 3DGS baseline)
  *
  * Conventions the paper leaves open (fixed identically on the GPU side):
  *   - camera: world->camera x_c = R x_w + t, OpenCV axes (x right, y down,
@@ -60,6 +62,11 @@ typedef struct {
     const double *lobe_angles; /* [n,m,2] (theta, phi) */
     const double *lobe_colors; /* [n,m,3] c_m */
     const double *lobe_betas;  /* [n,m]  raw b_m */
+    /* [n,16,3] degree-3 SH coefficients, or NULL.  Non-NULL selects the
+     * Gaussian-kernel + SH comparison mode: kernel exp(-m^2/2) for
+     * Mahalanobis distance m < 3, colour max(0, sum_k sh_k Y_k(V) + 1/2);
+     * betas, diffuse and the lobes are not read. */
+    const double *sh;
 } ob_splats;
 
 typedef struct {               /* gradients (or |contribution| sums); same shapes as ob_splats */
@@ -74,6 +81,51 @@ double ob_beta_kernel(double x, double b)
     if (!(x < 1.0)) return 0.0;
     if (x < 0.0) x = 0.0;
     return pow(1.0 - x, 4.0 * exp(b));
+}
+
+/* Real spherical harmonics of degree l <= 3 at the unit direction d, in the
+ * order (l, m) = (0,0), (1,-1), (1,0), (1,1), (2,-2), ..., (3,3), written
+ * from their definition: with cos(th) = d_z and ph = atan2(d_y, d_x),
+ *   Y_l^0 = K_l^0 P_l^0(cos th),
+ *   Y_l^m = sqrt(2) K_l^m cos(m ph) P_l^m(cos th)      (m > 0),
+ *   Y_l^m = sqrt(2) K_l^|m| sin(|m| ph) P_l^|m|(cos th) (m < 0),
+ *   K_l^m = sqrt((2l + 1) / (4 pi) (l - m)! / (l + m)!),
+ * where the associated Legendre functions P_l^m carry the Condon-Shortley
+ * phase (-1)^m. */
+static double assoc_legendre(int l, int m, double x)
+{
+    double s = sqrt(1.0 - x * x);
+    switch (10 * l + m) {
+    case 0: return 1.0;
+    case 10: return x;
+    case 11: return -s;
+    case 20: return 0.5 * (3.0 * x * x - 1.0);
+    case 21: return -3.0 * x * s;
+    case 22: return 3.0 * s * s;
+    case 30: return 0.5 * (5.0 * x * x * x - 3.0 * x);
+    case 31: return -1.5 * (5.0 * x * x - 1.0) * s;
+    case 32: return 15.0 * x * s * s;
+    case 33: return -15.0 * s * s * s;
+    }
+    return 0.0;
+}
+
+static double factorial(int k) { double f = 1.0; for (int i = 2; i <= k; ++i) f *= i; return f; }
+
+void ob_sh_basis3(const double *d, double *Y)
+{
+    double ct = d[2], ph = atan2(d[1], d[0]);
+    int k = 0;
+    for (int l = 0; l <= 3; ++l)
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double K = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * factorial(l - am) / factorial(l + am));
+            double P = assoc_legendre(l, am, ct);
+            if (m == 0) Y[k] = K * P;
+            else if (m > 0) Y[k] = sqrt(2.0) * K * cos(m * ph) * P;
+            else Y[k] = sqrt(2.0) * K * sin(am * ph) * P;
+            ++k;
+        }
 }
 
 /* Unit-quaternion rotation matrix (w,x,y,z), row-major.  q is normalised here. */
@@ -160,9 +212,11 @@ static void project_one(const ob_splats *s, int64_t i, const ob_camera *cam, ob_
 
     f->mean2d[0] = cam->fx * tx / tz + cam->cx;
     f->mean2d[1] = cam->fy * ty / tz + cam->cy;
-    /* the exact axis-aligned bounding box of {d : d^T Sigma'^{-1} d <= 1} */
-    f->extent[0] = sqrt(f->cov[0]);
-    f->extent[1] = sqrt(f->cov[2]);
+    /* the exact axis-aligned bounding box of {d : d^T Sigma'^{-1} d <= 1}
+     * (of the 3-sigma ellipse, d^T Sigma'^{-1} d <= 9, in the comparison mode) */
+    double ext = s->sh ? 3.0 : 1.0;
+    f->extent[0] = ext * sqrt(f->cov[0]);
+    f->extent[1] = ext * sqrt(f->cov[2]);
 
     /* pixel centres (u + 0.5) inside [mu' - e, mu' + e], clipped to the image */
     double xl = ceil(f->mean2d[0] - f->extent[0] - 0.5), xh = floor(f->mean2d[0] + f->extent[0] - 0.5);
@@ -178,7 +232,7 @@ static void project_one(const ob_splats *s, int64_t i, const ob_camera *cam, ob_
         f->bbox[2] = (int32_t)yl; f->bbox[3] = (int32_t)yh;
     }
 
-    f->beta = 4.0 * exp(s->betas[i]);
+    f->beta = s->sh ? 0.0 : 4.0 * exp(s->betas[i]);
 
     /* Spherical Beta colour, Sec. 3.3 Eq. (8) */
     double campos[3];
@@ -186,6 +240,17 @@ static void project_one(const ob_splats *s, int64_t i, const ob_camera *cam, ob_
     double v[3] = {mu[0] - campos[0], mu[1] - campos[1], mu[2] - campos[2]};
     f->vlen = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     for (int k = 0; k < 3; ++k) f->vdir[k] = v[k] / f->vlen;
+    if (s->sh) {  /* comparison mode: SH colour, offset by 1/2 and clamped at 0 */
+        double Y[16];
+        ob_sh_basis3(f->vdir, Y);
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.5;
+            for (int k = 0; k < 16; ++k) acc += Y[k] * s->sh[(i * 16 + k) * 3 + c];
+            f->color[c] = acc > 0.0 ? acc : 0.0;
+        }
+        f->valid = 1;
+        return;
+    }
     for (int c = 0; c < 3; ++c) f->color[c] = s->diffuse[3 * i + c];
     for (int m = 0; m < s->m; ++m) {
         double th = s->lobe_angles[2 * (i * s->m + m)], ph = s->lobe_angles[2 * (i * s->m + m) + 1];
@@ -290,8 +355,14 @@ static int64_t composite_pixel(const ob_splats *s, const ob_scene *sc, double px
         const ob_fwd *f = &sc->fw[i];
         double dx = px - f->mean2d[0], dy = py - f->mean2d[1];
         double r2 = f->conic[0] * dx * dx + 2.0 * f->conic[1] * dx * dy + f->conic[2] * dy * dy;
-        if (!(r2 < 1.0)) continue;                 /* bounded support: exactly zero */
-        double B = pow(1.0 - r2, f->beta);
+        double B;
+        if (s->sh) {                               /* Gaussian, cut at 3 sigma */
+            if (!(r2 < 9.0)) continue;
+            B = exp(-0.5 * r2);
+        } else {
+            if (!(r2 < 1.0)) continue;             /* bounded support: exactly zero */
+            B = pow(1.0 - r2, f->beta);
+        }
         double a = s->opacities[i] * B;
         int clamped = 0;
         if (a > alpha_max) { a = alpha_max; clamped = 1; }
@@ -547,6 +618,7 @@ int ob_render_bwd(const ob_splats *s, const ob_camera *cam, double alpha_max, do
                   ob_grads *grads, ob_grads *abs_sum)
 {
     ob_scene sc;
+    if (s->sh) return -2;  /* the comparison mode is forward only */
     if (scene_build(s, cam, &sc)) return -1;
     int64_t cap = sc.n_order > 0 ? sc.n_order : 1;
     int64_t chunk = 256;

@@ -179,6 +179,21 @@ def config4(n: int = 6_000_000, n_views: int = 32):
 CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
 
 
+def gaussian_sh(scene: dict, seed: int = 7, scale_factor: float = 1.0) -> dict:
+    """The scene as input of the Gaussian-kernel + SH comparison mode: the same
+    centres, rotations and opacities, scales times `scale_factor` (1/3 puts
+    the 3-sigma ellipse on the Beta kernel's support), and degree-3 SH
+    coefficients [n, 16, 3]: DC ~ N(0, 0.6), higher orders ~ N(0, 0.15)."""
+    rng = np.random.default_rng(seed)
+    n = scene["means"].shape[0]
+    sh = rng.normal(0.0, 0.15, size=(n, 16, 3))
+    sh[:, 0, :] = rng.normal(0.0, 0.6, size=(n, 3))
+    out = dict(scene)
+    out["scales"] = np.ascontiguousarray(scene["scales"] * np.float32(scale_factor), dtype=np.float32)
+    out["sh"] = np.ascontiguousarray(sh, dtype=np.float32)
+    return out
+
+
 def subset(scene: dict, idx) -> dict:
     """Rows `idx` of every array of a scene."""
     return {k: np.ascontiguousarray(v[idx]) for k, v in scene.items()}

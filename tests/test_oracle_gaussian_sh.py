@@ -1,0 +1,78 @@
+"""Pins of the oracle's Gaussian-kernel + SH comparison mode (forward only):
+the real spherical harmonics against scipy's complex ones, and a splat on
+the optical axis against the closed form of its Gaussian footprint."""
+import numpy as np
+import pytest
+import scipy.special as sps
+
+import oracle
+from paper_2501_18630_amd import scenes
+
+
+def _scipy_real_sh(d):
+    th, ph = np.arccos(d[2]), np.arctan2(d[1], d[0])
+    out = []
+    for l in range(4):
+        for m in range(-l, l + 1):
+            z = sps.sph_harm_y(l, abs(m), th, ph)   # Condon-Shortley phase included
+            out.append(z.real if m == 0 else np.sqrt(2.0) * (z.real if m > 0 else z.imag))
+    return np.array(out)
+
+
+def test_sh_basis_matches_scipy():
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        np.testing.assert_allclose(oracle.sh_basis3(d), _scipy_real_sh(d), rtol=0, atol=1e-13)
+    # the poles and the equator (atan2 edge cases)
+    for d in ([0, 0, 1.0], [0, 0, -1.0], [1.0, 0, 0], [0, -1.0, 0]):
+        d = np.asarray(d)
+        np.testing.assert_allclose(oracle.sh_basis3(d), _scipy_real_sh(d), rtol=0, atol=1e-13)
+
+
+def _axis_splat(o, s, z, dc, bg):
+    one = lambda a: np.asarray([a], np.float32)
+    scene = dict(means=np.float32([[0.0, 0.0, z]]), scales=np.float32([[s, s, s]]),
+                 quats=np.float32([[1.0, 0.0, 0.0, 0.0]]), opacities=one(o), betas=one(0.0),
+                 diffuse=np.zeros((1, 3), np.float32), lobe_angles=np.zeros((1, 0, 2), np.float32),
+                 lobe_colors=np.zeros((1, 0, 3), np.float32), lobe_betas=np.zeros((1, 0), np.float32))
+    sh = np.zeros((1, 16, 3), np.float32)
+    sh[0, 0] = dc
+    sh[0, 5] = 0.3   # Y_2^-1 = -c yz vanishes on the axis (the view direction is +z)
+    scene["sh"] = sh
+    return scene
+
+
+def test_gaussian_footprint_closed_form():
+    # isotropic splat of scale s at depth z on the optical axis: Sigma' =
+    # (f s / z)^2 I, alpha = o exp(-m^2 / 2) with m = |pixel - centre| z / (f s),
+    # zero from m = 3 on; colour = max(0, dc Y_0^0 + 1/2) on the axis
+    o, s, z, f, W, H = 0.7, 0.2, 4.0, 40.0, 23, 19
+    dc = np.float32([0.8, -0.4, -3.0])
+    bg = np.float32([0.1, 0.2, 0.3])
+    scene = _axis_splat(o, s, z, dc, bg)
+    cam = scenes.camera(W, H, f=f, background=bg)
+    out = oracle.render(scene, cam, 0.99, 1e-4)
+    col = np.maximum(dc.astype(np.float64) * 0.5 / np.sqrt(np.pi) + 0.5, 0.0)
+    yy, xx = np.mgrid[0:H, 0:W]
+    d2 = (xx + 0.5 - W / 2.0) ** 2 + (yy + 0.5 - H / 2.0) ** 2
+    m2 = d2 * (z / (f * np.float64(np.float32(s)))) ** 2
+    alpha = np.where(m2 < 9.0, np.float64(np.float32(o)) * np.exp(-0.5 * m2), 0.0).ravel()
+    ref = col[None, :] * alpha[:, None] + (1.0 - alpha)[:, None] * bg.astype(np.float64)[None, :]
+    np.testing.assert_allclose(out["rgb"], ref, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(out["T"], 1.0 - alpha, rtol=0, atol=1e-12)
+    assert (alpha > 0).sum() > 20 and (alpha == 0).sum() > 20   # both sides of the 3-sigma cut are sampled
+    # the pixel box is the tight box of the 3-sigma circle, radius 3 f s / z
+    pr = oracle.project(scene, cam)
+    np.testing.assert_allclose(pr["extent"][0], 3.0 * f * np.float64(np.float32(s)) / z, rtol=1e-12)
+    inside = (alpha > 0).reshape(H, W)
+    ys, xs = np.nonzero(inside)
+    assert tuple(pr["bbox"][0]) == (xs.min(), xs.max(), ys.min(), ys.max())
+
+
+def test_gaussian_mode_is_forward_only():
+    scene = _axis_splat(0.5, 0.05, 4.0, np.float32([0.1, 0.1, 0.1]), None)
+    cam = scenes.camera(8, 8, f=10.0)
+    with pytest.raises(MemoryError):
+        oracle.render_bwd(scene, cam, 0.99, 1e-4, np.zeros((64, 3)))

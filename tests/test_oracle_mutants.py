@@ -10,7 +10,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_TESTS = ["tests/test_oracle_kernel_projection.py", "tests/test_oracle_render.py",
-             "tests/test_oracle_grad_bin.py"]
+             "tests/test_oracle_grad_bin.py", "tests/test_oracle_gaussian_sh.py"]
 
 MUTANTS = {
     "mean2d_adjoint_sign": ("sa.mean2d[0] = -adj_r2 * 2.0", "sa.mean2d[0] = adj_r2 * 2.0"),
@@ -26,7 +26,13 @@ MUTANTS = {
     "jacobian_sign": ("f->Jm[2] = -cam->fx * tx / (tz * tz);", "f->Jm[2] = cam->fx * tx / (tz * tz);"),
     "view_rotation_transposed": ("acc += f->Jm[3 * a + k] * W[3 * k + b];",
                                  "acc += f->Jm[3 * a + k] * W[3 * b + k];"),
-    "kernel_constant": ("f->beta = 4.0 * exp(s->betas[i]);", "f->beta = 3.5 * exp(s->betas[i]);"),
+    "kernel_constant": ("f->beta = s->sh ? 0.0 : 4.0 * exp(s->betas[i]);",
+                        "f->beta = s->sh ? 0.0 : 3.5 * exp(s->betas[i]);"),
+    "gaussian_exponent": ("B = exp(-0.5 * r2);", "B = exp(-r2);"),
+    "gaussian_cutoff": ("if (!(r2 < 9.0)) continue;", "if (!(r2 < 4.0)) continue;"),
+    "gaussian_extent": ("double ext = s->sh ? 3.0 : 1.0;", "double ext = s->sh ? 2.0 : 1.0;"),
+    "sh_legendre_phase": ("case 21: return -3.0 * x * s;", "case 21: return 3.0 * x * s;"),
+    "sh_offset": ("double acc = 0.5;", "double acc = 0.0;"),
     "quaternion_sign": ("R[1] = 2.0 * (x * y - w * z);", "R[1] = 2.0 * (x * y + w * z);"),
     "termination_rule": ("        last = i;\n        if (T < t_eps) break;",
                          "        last = i;\n        if (T_prev * (1.0 - a) < t_eps * 0.5) break;"),
