@@ -129,6 +129,52 @@ def stage_times(rast, step, steps):
     return {k: v / steps for k, v in acc.items()}
 
 
+def forward_stage_times(rast, params, outputs, steps):
+    """Average ms of preprocess, bin/sort and raster forward (HIP events on
+    torch's current stream, the library's stream)."""
+    import torch
+    names = ("preprocess", "bin_sort", "raster_fwd")
+    acc = {k: 0.0 for k in names}
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        rast.preprocess(params)
+        ev[1].record()
+        rast.bin_sort()
+        ev[2].record()
+        rast.render_fwd(*outputs)
+        ev[3].record()
+        torch.cuda.synchronize()
+        for k, name in enumerate(names):
+            acc[name] += ev[k].elapsed_time(ev[k + 1])
+    return {k: v / steps for k, v in acc.items()}
+
+
+def gaussian_sh_times(scene, cams, cfg, steps):
+    """Forward of the Gaussian-kernel + degree-3 SH comparison mode on the same
+    scene and views: with the same scales (its 3-sigma support is 3x as wide
+    as the Beta kernel's r < 1) and with scales / 3 (the same support)."""
+    import torch
+    from paper_2501_18630_amd import renderer, scenes
+    n = scene["means"].shape[0]
+    out = {}
+    for name, factor in (("same_scales", 1.0), ("same_support", 1.0 / 3.0)):
+        g = scenes.gaussian_sh(scene, seed=7, scale_factor=factor)
+        params = renderer.to_device(g)
+        gcfg = renderer.RasterConfig(tile_w=cfg.tile_w, tile_h=cfg.tile_h, batch=cfg.batch, kernel="gaussian_sh")
+        rast = renderer.Rasterizer(cams, n, g["lobe_betas"].shape[1], gcfg, headroom=1.05)
+        outputs = rast.forward(params)
+        pairs = int(rast.counts[1].item())
+        t = forward_stage_times(rast, params, outputs, steps)
+        assert int(rast.overflow.item()) == 0
+        out[name] = {k + "_ms": round(v, 4) for k, v in t.items()}
+        out[name]["fwd_ms"] = round(sum(t.values()), 4)
+        out[name]["pairs"] = pairs
+        del rast, params, outputs
+        torch.cuda.empty_cache()
+    return out
+
+
 def composite_loss_times(rast, step, steps, lam_ssim=0.2, lam_reg=0.01):
     """Average ms of the composite-loss kernels of Sec. 3.4 on the step's
     rendered images (the benchmark step itself uses L1): the photometric term
@@ -295,6 +341,9 @@ def main():
     log(f"composite loss (ms): photometric {t_photo:.3f}, regularisers {t_reg:.3f}")
     t_reloc, t_noise, n_moved = mcmc_times(params, n, m, 3)
     log(f"mcmc (ms): relocate {t_reloc:.3f} ({n_moved} moved), noise {t_noise:.3f}")
+    gsh = gaussian_sh_times(scene, cams, cfg, 3)
+    gsh["beta_fwd_ms"] = round(st["preprocess"] + st["bin_sort"] + st["raster_fwd"], 4)
+    log(f"gaussian+SH forward (ms): {gsh}")
 
     mpix = X / t_batched / 1e6
     q_floats = 15 + 6 * m
@@ -339,6 +388,7 @@ def main():
                            "photometric_GBs": round(12 * 3 * X / (t_photo * 1e-3) / 1e9, 1)},
         # not in the step: the MCMC step of Sec. 3.4 over all splats (dead: o <= 0.005)
         "mcmc": {"relocate_ms": round(t_reloc, 4), "noise_ms": round(t_noise, 4), "relocated": n_moved},
+        "gaussian_sh_forward": gsh,
         "work": wc,
         "global_atomics": {"per_raster_bwd": n_atomics,
                            "per_s": round(n_atomics / (st["raster_bwd"] * 1e-3), 1),

@@ -127,6 +127,16 @@ typedef struct {
 #define DBS_FLAG_B_BELOW 8u
 #define DBS_FLAG_B_ABOVE 16u
 
+/* Gaussian-kernel + spherical-harmonics comparison mode: the baseline the
+ * paper compares against (3D Gaussian Splatting's kernel and degree-3 SH
+ * colour, Sec. 3.3 and Sec. 4), rendered by the same pipeline.  The records
+ * are written by dbs_preprocess_gaussian_sh; dbs_render_fwd then takes
+ * alpha = min(alpha_max, o exp(-m^2 / 2)) for Mahalanobis distance m < 3
+ * (the 3-sigma ellipse is the support).  Forward only: dbs_preprocess and
+ * the reverse calls reject the flag, and it cannot be combined with the
+ * decomposition flags. */
+#define DBS_FLAG_GAUSSIAN_SH 32u
+
 /* Fills *cfg with the defaults above (16x16 tiles, batch 256, persistent, no
  * decomposition). */
 void dbs_default_cfg(dbs_raster_cfg *cfg);
@@ -163,6 +173,22 @@ dbs_status dbs_preprocess(const dbs_splats *splats /*[host] struct of device poi
                           const dbs_raster_cfg *cfg /*[host]*/,
                           void *projected, size_t projected_bytes,
                           int64_t *counts /* device int64[2] or NULL */, void *stream);
+
+/* Projection for DBS_FLAG_GAUSSIAN_SH (cfg->flags must hold it): the same
+ * records as dbs_preprocess, with the 3-sigma ellipse as the support (conic
+ * Sigma'^{-1} / 9, pixel box mu' +- 3 (sqrt Sigma'00, sqrt Sigma'11)) and the
+ * colour max(0, sum_k sh_k Y_k(V) + 1/2) from the 16 real spherical
+ * harmonics Y_k of degree <= 3 (order l = 0..3, m = -l..l, Condon-Shortley
+ * phase) at the view direction V = (mu - camera centre) / |mu - camera
+ * centre|.  Reads means, scales, quats and opacities of `splats` (m, betas,
+ * diffuse and lobes are ignored) and sh: device [n, 16, 3] FP32, coefficient
+ * k of channel c at sh[(i * 16 + k) * 3 + c].  Other arguments and errors as
+ * dbs_preprocess; sh == NULL with n > 0 is DBS_ERR_INVALID_ARGUMENT. */
+dbs_status dbs_preprocess_gaussian_sh(const dbs_splats *splats /*[host] struct of device pointers*/,
+                                      const float *sh, const dbs_camera *cams /*[host]*/, int32_t n_views,
+                                      const dbs_raster_cfg *cfg /*[host]*/, void *projected,
+                                      size_t projected_bytes, int64_t *counts /* device int64[2] or NULL */,
+                                      void *stream);
 
 /* Tile lists (Sec. 3.2, sorting by depth before Eq. 6): every visible record
  * is listed in each tile its pixel box overlaps; each list is ordered by the

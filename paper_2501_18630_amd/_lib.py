@@ -20,12 +20,13 @@ FLAG_DIFFUSE_ONLY = 2
 FLAG_SPECULAR_ONLY = 4
 FLAG_B_BELOW = 8
 FLAG_B_ABOVE = 16
+FLAG_GAUSSIAN_SH = 32
 
 PARAMS = ("means", "scales", "quats", "opacities", "betas", "diffuse",
           "lobe_angles", "lobe_colors", "lobe_betas")
 
 EXPORTS = ("dbs_default_cfg", "dbs_projected_bytes", "dbs_bins_bytes", "dbs_workspace_bytes",
-           "dbs_preprocess", "dbs_bin_sort", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
+           "dbs_preprocess", "dbs_preprocess_gaussian_sh", "dbs_bin_sort", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
            "dbs_photometric_loss", "dbs_regularizer", "dbs_mcmc_workspace_bytes", "dbs_mcmc_relocate",
            "dbs_mcmc_noise",
            "dbs_raster_bwd", "dbs_raster_bwd_count", "dbs_project_bwd", "dbs_render_stats",
@@ -71,6 +72,7 @@ def _declare(lib):
     lib.dbs_workspace_bytes.argtypes = [I64, I32, I64, P, P]
     lib.dbs_workspace_bytes.restype = SZ
     lib.dbs_preprocess.argtypes = [P, P, I32, P, P, SZ, P, P]
+    lib.dbs_preprocess_gaussian_sh.argtypes = [P, P, P, I32, P, P, SZ, P, P]
     lib.dbs_bin_sort.argtypes = [P, P, I32, P, I64, I64, P, SZ, P, SZ, P, P]
     lib.dbs_render_fwd.argtypes = [P, P, P, I32, P, I64, P, P, P, P]
     lib.dbs_render_bwd.argtypes = [P, P, P, P, I32, P, P, P, P, P, P]
@@ -87,7 +89,7 @@ def _declare(lib):
     lib.dbs_mcmc_noise.argtypes = [P, P, C.c_float, C.c_float, C.c_float, P]
     lib.dbs_projected_layout.argtypes = [P, I64, I32] + [C.POINTER(C.c_void_p)] * 5
     lib.dbs_bins_layout.argtypes = [P, I64, P, I32, P] + [C.POINTER(C.c_void_p)] * 3 + [C.POINTER(C.c_int64)]
-    for f in ("dbs_preprocess", "dbs_bin_sort", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
+    for f in ("dbs_preprocess", "dbs_preprocess_gaussian_sh", "dbs_bin_sort", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
               "dbs_photometric_loss", "dbs_regularizer", "dbs_mcmc_workspace_bytes", "dbs_mcmc_relocate",
            "dbs_mcmc_noise", "dbs_raster_bwd", "dbs_raster_bwd_count", "dbs_project_bwd", "dbs_render_stats",
               "dbs_projected_layout", "dbs_bins_layout"):

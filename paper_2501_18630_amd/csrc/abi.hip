@@ -40,8 +40,10 @@ static dbs_status check_cfg(const dbs_raster_cfg *cfg)
     if (!(cfg->alpha_max > 0.0f && cfg->alpha_max < 1.0f)) return DBS_ERR_INVALID_ARGUMENT;
     if (!(cfg->t_eps >= 0.0f && cfg->t_eps < 1.0f)) return DBS_ERR_INVALID_ARGUMENT;
     const uint32_t known = DBS_FLAG_PERSISTENT | DBS_FLAG_DIFFUSE_ONLY | DBS_FLAG_SPECULAR_ONLY | DBS_FLAG_B_BELOW |
-                           DBS_FLAG_B_ABOVE;
+                           DBS_FLAG_B_ABOVE | DBS_FLAG_GAUSSIAN_SH;
     if ((cfg->flags & ~known) != 0) return DBS_ERR_INVALID_ARGUMENT;
+    if ((cfg->flags & DBS_FLAG_GAUSSIAN_SH) && (cfg->flags & ~(DBS_FLAG_GAUSSIAN_SH | DBS_FLAG_PERSISTENT)))
+        return DBS_ERR_INVALID_ARGUMENT;
     if ((cfg->flags & DBS_FLAG_DIFFUSE_ONLY) && (cfg->flags & DBS_FLAG_SPECULAR_ONLY)) return DBS_ERR_INVALID_ARGUMENT;
     if ((cfg->flags & DBS_FLAG_B_BELOW) && (cfg->flags & DBS_FLAG_B_ABOVE)) return DBS_ERR_INVALID_ARGUMENT;
     if (!finite(cfg->b_split)) return DBS_ERR_INVALID_ARGUMENT;
@@ -79,8 +81,9 @@ static SplatPtrs splat_ptrs(const dbs_splats *s)
     return p;
 }
 
+// render modes without a reverse pass
 constexpr uint32_t kDecompositionFlags = DBS_FLAG_DIFFUSE_ONLY | DBS_FLAG_SPECULAR_ONLY | DBS_FLAG_B_BELOW |
-                                         DBS_FLAG_B_ABOVE;
+                                         DBS_FLAG_B_ABOVE | DBS_FLAG_GAUSSIAN_SH;
 
 static dbs_status hip_status(hipError_t e) { return e == hipSuccess ? DBS_OK : DBS_ERR_HIP; }
 
@@ -134,14 +137,38 @@ dbs_status dbs_preprocess(const dbs_splats *splats, const dbs_camera *cams, int3
     DBS_TRY(check_splats(splats));
     DBS_TRY(check_cams(cams, n_views));
     DBS_TRY(check_cfg(cfg));
+    if (cfg->flags & DBS_FLAG_GAUSSIAN_SH) return DBS_ERR_INVALID_ARGUMENT;  // needs the SH coefficients
     DBS_TRY(check_sizes(splats->n, n_views));
     if (!projected) return DBS_ERR_INVALID_ARGUMENT;
     if (projected_bytes < proj_layout(splats->n, n_views).total) return DBS_ERR_CAPACITY;
     hipStream_t s = (hipStream_t)stream;
     ProjPtrs P = proj_ptrs(projected, splats->n, n_views);
     DBS_TRY(hip_status(launch_upload_views(cams, n_views, cfg->tile_w, cfg->tile_h, P, splats->n, splats->m, s)));
-    return hip_status(launch_preprocess(splat_ptrs(splats), P, n_views, cfg->tile_w, cfg->tile_h, cfg->flags,
-                                        cfg->b_split, counts, s));
+    return hip_status(launch_preprocess(splat_ptrs(splats), nullptr, P, n_views, cfg->tile_w, cfg->tile_h,
+                                        cfg->flags, cfg->b_split, counts, s));
+}
+
+dbs_status dbs_preprocess_gaussian_sh(const dbs_splats *splats, const float *sh, const dbs_camera *cams,
+                                      int32_t n_views, const dbs_raster_cfg *cfg, void *projected,
+                                      size_t projected_bytes, int64_t *counts, void *stream)
+{
+    if (!splats) return DBS_ERR_INVALID_ARGUMENT;
+    if (splats->n < 0) return DBS_ERR_INVALID_ARGUMENT;
+    if (splats->n > 0 && (!splats->means || !splats->scales || !splats->quats || !splats->opacities || !sh))
+        return DBS_ERR_INVALID_ARGUMENT;
+    DBS_TRY(check_cams(cams, n_views));
+    DBS_TRY(check_cfg(cfg));
+    if (!(cfg->flags & DBS_FLAG_GAUSSIAN_SH)) return DBS_ERR_INVALID_ARGUMENT;
+    DBS_TRY(check_sizes(splats->n, n_views));
+    if (!projected) return DBS_ERR_INVALID_ARGUMENT;
+    if (projected_bytes < proj_layout(splats->n, n_views).total) return DBS_ERR_CAPACITY;
+    hipStream_t s = (hipStream_t)stream;
+    ProjPtrs P = proj_ptrs(projected, splats->n, n_views);
+    SplatPtrs sp = splat_ptrs(splats);
+    sp.m = 0;
+    DBS_TRY(hip_status(launch_upload_views(cams, n_views, cfg->tile_w, cfg->tile_h, P, splats->n, 0, s)));
+    return hip_status(launch_preprocess(sp, sh, P, n_views, cfg->tile_w, cfg->tile_h, cfg->flags, cfg->b_split,
+                                        counts, s));
 }
 
 dbs_status dbs_bin_sort(const void *projected, const dbs_camera *cams, int32_t n_views, const dbs_raster_cfg *cfg,
@@ -256,6 +283,7 @@ dbs_status dbs_render_stats(const void *projected, const void *bins, const dbs_c
 {
     DBS_TRY(check_cams(cams, n_views));
     DBS_TRY(check_cfg(cfg));
+    if (cfg->flags & DBS_FLAG_GAUSSIAN_SH) return DBS_ERR_UNSUPPORTED;
     DBS_TRY(check_sizes(n, n_views));
     if (!projected || !bins || !final_T || !last_index || !out) return DBS_ERR_INVALID_ARGUMENT;
     const int64_t n_tiles = total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h);

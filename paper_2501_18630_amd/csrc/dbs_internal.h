@@ -227,8 +227,9 @@ int64_t total_tiles(const dbs_camera *cams, int32_t n_views, int tile_w, int til
 // preprocess.hip
 hipError_t launch_upload_views(const dbs_camera *cams, int32_t n_views, int tile_w, int tile_h,
                                ProjPtrs P, int64_t n, int32_t m, hipStream_t s);
-hipError_t launch_preprocess(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, int tile_w, int tile_h,
-                             uint32_t flags, float b_split, int64_t *counts, hipStream_t s);
+// sh != nullptr selects the Gaussian-kernel + SH comparison mode ([n, 16, 3] coefficients)
+hipError_t launch_preprocess(const SplatPtrs &sp, const float *sh, ProjPtrs P, int32_t n_views, int tile_w,
+                             int tile_h, uint32_t flags, float b_split, int64_t *counts, hipStream_t s);
 // sort.hip
 hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_t n_views,
                            int64_t cap, int64_t n_tiles, int tile_w, int tile_h,

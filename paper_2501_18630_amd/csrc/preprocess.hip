@@ -51,8 +51,39 @@ __device__ inline uint64_t wave_sum_u64(uint64_t v)
     return v;
 }
 
-template <int M>
-__global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
+// Real spherical harmonics of degree <= 3 at the unit direction (x, y, z), in
+// the order l = 0..3, m = -l..l, with the Condon-Shortley phase: each constant
+// is the normalisation sqrt((2l + 1) / (4 pi) (l - |m|)! / (l + |m|)!) (times
+// sqrt 2 for m != 0) with the associated Legendre polynomial's own factor
+// folded in, and the polynomials in x, y, z are the Cartesian forms of
+// r^l P_l^|m|(cos theta) cos(m phi) (m > 0) or sin(|m| phi) (m < 0).
+__device__ __forceinline__ void sh_basis3(float x, float y, float z, float Y[16])
+{
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = 0.28209479177387814f;
+    Y[1] = -0.48860251190291992f * y;
+    Y[2] = 0.48860251190291992f * z;
+    Y[3] = -0.48860251190291992f * x;
+    Y[4] = 1.0925484305920792f * x * y;
+    Y[5] = -1.0925484305920792f * y * z;
+    Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+    Y[7] = -1.0925484305920792f * x * z;
+    Y[8] = 0.54627421529603959f * (xx - yy);
+    Y[9] = -0.59004358992664352f * y * (3.0f * xx - yy);
+    Y[10] = 2.8906114426405538f * x * y * z;
+    Y[11] = -0.45704579946446572f * y * (4.0f * zz - xx - yy);
+    Y[12] = 0.37317633259011540f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -0.45704579946446572f * x * (4.0f * zz - xx - yy);
+    Y[14] = 1.4453057213202769f * z * (xx - yy);
+    Y[15] = -0.59004358992664352f * x * (xx - 3.0f * yy);
+}
+
+// GSH: the Gaussian-kernel + SH comparison mode.  The support is the 3-sigma
+// ellipse, so the stored conic is Sigma'^{-1} / 9 (r^2 < 1 there, and the
+// raster takes exp(-4.5 r^2)) and the pixel box is 3 times as wide; the colour
+// is max(0, sum_k sh_k Y_k(V) + 1/2).
+template <int M, bool GSH>
+__global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const float *sh, ProjPtrs P, int32_t n_views,
                                                          int32_t lw, int32_t lh, uint32_t flags, float b_split)
 {
     const int64_t n = sp.n;
@@ -88,9 +119,10 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
                 Sig[b][a] = acc;
             }
         const float opac = sp.opacities[i];
-        const float beta = 4.0f * expf(sp.betas[i]);
-        const float c0r = diffuse_on ? sp.diffuse[3 * i] : 0.0f, c0g = diffuse_on ? sp.diffuse[3 * i + 1] : 0.0f,
-                    c0b = diffuse_on ? sp.diffuse[3 * i + 2] : 0.0f;
+        const float beta = GSH ? 0.0f : 4.0f * expf(sp.betas[i]);
+        const bool c0_on = diffuse_on && !GSH;
+        const float c0r = c0_on ? sp.diffuse[3 * i] : 0.0f, c0g = c0_on ? sp.diffuse[3 * i + 1] : 0.0f,
+                    c0b = c0_on ? sp.diffuse[3 * i + 2] : 0.0f;
         float lr[M > 0 ? M : 1][3], lc[M > 0 ? M : 1][3], lbeta[M > 0 ? M : 1];
 #pragma unroll
         for (int mm = 0; mm < M; ++mm) {
@@ -141,7 +173,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
                 if (det > 0.0) {
                     const double mx = fx * tx * iz + (double)V.cx;
                     const double my = fy * ty * iz + (double)V.cy;
-                    const double ex = sqrt(c00), ey = sqrt(c11);
+                    const double ext = GSH ? 3.0 : 1.0;
+                    const double ex = ext * sqrt(c00), ey = ext * sqrt(c11);
                     double xl = ceil(mx - ex - 0.5), xh = floor(mx + ex - 0.5);
                     double yl = ceil(my - ey - 0.5), yh = floor(my + ey - 0.5);
                     xl = fmax(xl, 0.0);
@@ -152,7 +185,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
                         const int ixl = (int)xl, ixh = (int)xh, iyl = (int)yl, iyh = (int)yh;
                         bb = make_short4((short)ixl, (short)ixh, (short)iyl, (short)iyh);
                         ntiles = (uint32_t)(((ixh >> lw) - (ixl >> lw) + 1) * ((iyh >> lh) - (iyl >> lh) + 1));
-                        const double idet = 1.0 / det;
+                        const double idet = 1.0 / (GSH ? 9.0 * det : det);
                         RasterRec rr;
                         rr.cx = mx;
                         rr.cy = my;
@@ -169,6 +202,21 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, ProjPtrs 
                         const double ivl = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
                         const float dx = (float)(vx * ivl), dy = (float)(vy * ivl), dz = (float)(vz * ivl);
                         float cr = c0r, cg = c0g, cb = c0b;
+                        if (GSH) {
+                            float Y[16];
+                            sh_basis3(dx, dy, dz, Y);
+                            const float *c = sh + i * 48;
+                            cr = cg = cb = 0.5f;
+#pragma unroll
+                            for (int k = 0; k < 16; ++k) {
+                                cr = __fmaf_rn(Y[k], c[3 * k], cr);
+                                cg = __fmaf_rn(Y[k], c[3 * k + 1], cg);
+                                cb = __fmaf_rn(Y[k], c[3 * k + 2], cb);
+                            }
+                            cr = fmaxf(cr, 0.0f);
+                            cg = fmaxf(cg, 0.0f);
+                            cb = fmaxf(cb, 0.0f);
+                        }
 #pragma unroll
                         for (int mm = 0; mm < M; ++mm) {
                             const float d = lr[mm][0] * dx + lr[mm][1] * dy + lr[mm][2] * dz;
@@ -250,8 +298,8 @@ hipError_t launch_upload_views(const dbs_camera *cams, int32_t n_views, int tile
     return hipGetLastError();
 }
 
-hipError_t launch_preprocess(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, int tile_w, int tile_h,
-                             uint32_t flags, float b_split, int64_t *counts_out, hipStream_t s)
+hipError_t launch_preprocess(const SplatPtrs &sp, const float *sh, ProjPtrs P, int32_t n_views, int tile_w,
+                             int tile_h, uint32_t flags, float b_split, int64_t *counts_out, hipStream_t s)
 {
     if (sp.n > 0) {
         // tile sizes are powers of two: pixel -> tile is a shift
@@ -260,12 +308,18 @@ hipError_t launch_preprocess(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, i
         while ((1 << lh) < tile_h) ++lh;
         if ((1 << lw) != tile_w || (1 << lh) != tile_h) return hipErrorInvalidValue;
         dim3 grid((unsigned)ceil_div(sp.n, 256));
+        if (sh) {
+            preprocess_kernel<0, true><<<grid, 256, 0, s>>>(sp, sh, P, n_views, lw, lh, flags, b_split);
+        } else {
         switch (sp.m) {
-#define DBS_PRE(MM) case MM: preprocess_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, lw, lh, flags, b_split); break;
+#define DBS_PRE(MM)                                                                                          \
+    case MM: preprocess_kernel<MM, false><<<grid, 256, 0, s>>>(sp, nullptr, P, n_views, lw, lh, flags, b_split); \
+        break;
             DBS_PRE(0) DBS_PRE(1) DBS_PRE(2) DBS_PRE(3) DBS_PRE(4)
             DBS_PRE(5) DBS_PRE(6) DBS_PRE(7) DBS_PRE(8)
 #undef DBS_PRE
             default: return hipErrorInvalidValue;
+        }
         }
     }
     if (counts_out) copy_counts_kernel<<<1, 64, 0, s>>>(P.hdr, counts_out);

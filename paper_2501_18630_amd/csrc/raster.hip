@@ -355,7 +355,10 @@ __device__ __forceinline__ void mark_shared_steps(const uint8_t *rows, const int
 
 // ---------------------------------------------------------------- forward
 
-template <int TW, int TH, int BATCH>
+// GAUSS: the Gaussian-kernel comparison mode.  Its records carry the conic
+// of the 3-sigma ellipse (Sigma'^{-1} / 9), so r^2 < 1 is the support and
+// the kernel is exp(-m^2 / 2) = exp(-4.5 r^2) = exp2(-4.5 log2(e) r^2).
+template <int TW, int TH, int BATCH, bool GAUSS = false>
 __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
 {
     using G = Geo<TW, TH>;
@@ -404,7 +407,8 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                 if (act && r2 < 1.0) {
                     const float2 ob = unpack2(bb.y);
                     float lg;
-                    const float B = eval_kernel((float)(1.0 - r2), ob.y, &lg);
+                    const float B = GAUSS ? __builtin_amdgcn_exp2f(-6.4921276840003350f * (float)r2)
+                                          : eval_kernel((float)(1.0 - r2), ob.y, &lg);
                     const float alpha = fminf(a.alpha_max, __fmul_rn(ob.x, B));
                     const float wgt = alpha * T;
                     const float4 cc = s_col[k];
@@ -765,16 +769,19 @@ template <int TW, int TH, int BATCH>
 struct Kern {
     static constexpr int BWD_BATCH = BATCH < 128 ? BATCH : 128;
     static void *fwd() { return (void *)raster_fwd_kernel<TW, TH, BATCH>; }
+    static void *fwd_gauss() { return (void *)raster_fwd_kernel<TW, TH, BATCH, true>; }
     static void *bwd() { return (void *)raster_bwd_kernel<TW, TH, BWD_BATCH>; }
     static void *bwd_count() { return (void *)raster_bwd_kernel<TW, TH, BWD_BATCH, true>; }
 };
 
 struct Entry {
     int tw, th, batch;
-    void *fwd, *bwd, *bwd_count;
+    void *fwd, *bwd, *bwd_count, *fwd_gauss;
 };
 
-#define DBS_ENTRY(TW, TH, B) {TW, TH, B, Kern<TW, TH, B>::fwd(), Kern<TW, TH, B>::bwd(), Kern<TW, TH, B>::bwd_count()}
+#define DBS_ENTRY(TW, TH, B)                                                                             \
+    {TW, TH, B, Kern<TW, TH, B>::fwd(), Kern<TW, TH, B>::bwd(), Kern<TW, TH, B>::bwd_count(),           \
+     Kern<TW, TH, B>::fwd_gauss()}
 const Entry kEntries[] = {
     DBS_ENTRY(16, 16, 64),  DBS_ENTRY(16, 16, 128), DBS_ENTRY(16, 16, 256),
     DBS_ENTRY(16, 8, 64),   DBS_ENTRY(16, 8, 128),  DBS_ENTRY(16, 8, 256),
@@ -862,7 +869,8 @@ hipError_t launch_raster_fwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
     a.image = image;
     a.final_T = final_T;
     a.last_index = last_index;
-    return launch(e->fwd, cfg.tile_w * cfg.tile_h, a, n_tiles, s);
+    return launch((cfg.flags & DBS_FLAG_GAUSSIAN_SH) ? e->fwd_gauss : e->fwd, cfg.tile_w * cfg.tile_h, a, n_tiles,
+                  s);
 }
 
 hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views, int64_t n_tiles,

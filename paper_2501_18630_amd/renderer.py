@@ -39,11 +39,15 @@ class RasterConfig:
     color: str = "full"
     b_range: str = "all"
     b_split: float = 0.0
+    # "beta" (the method) or "gaussian_sh": the comparison mode with a
+    # Gaussian kernel and degree-3 SH colour (forward only; params["sh"])
+    kernel: str = "beta"
 
     def to_c(self) -> _lib.RasterCfg:
         flags = _lib.FLAG_PERSISTENT if self.persistent else 0
         flags |= {"full": 0, "diffuse": _lib.FLAG_DIFFUSE_ONLY, "specular": _lib.FLAG_SPECULAR_ONLY}[self.color]
         flags |= {"all": 0, "below": _lib.FLAG_B_BELOW, "above": _lib.FLAG_B_ABOVE}[self.b_range]
+        flags |= {"beta": 0, "gaussian_sh": _lib.FLAG_GAUSSIAN_SH}[self.kernel]
         return _lib.RasterCfg(self.tile_w, self.tile_h, self.batch, self.t_eps, self.alpha_max, flags, self.b_split)
 
 
@@ -59,8 +63,9 @@ def make_cameras(cams) -> C.Array:
 
 def to_device(scene: dict, device="cuda") -> dict:
     """numpy scene -> dict of contiguous float32 tensors on `device`."""
+    keys = PARAMS + (("sh",) if "sh" in scene else ())
     return {k: torch.as_tensor(np.ascontiguousarray(scene[k], np.float32), device=device).contiguous()
-            for k in PARAMS}
+            for k in keys}
 
 
 def _splats_c(params: dict, n: int, m: int) -> _lib.Splats:
@@ -136,6 +141,15 @@ class Rasterizer:
     # ---- the four calls ----
     def preprocess(self, params: dict):
         sp = _splats_c(params, self.n, self.m)
+        if self.cfg.kernel == "gaussian_sh":
+            sh = params["sh"]
+            if sh.dtype != torch.float32 or not sh.is_contiguous() or not sh.is_cuda or sh.numel() != 48 * self.n:
+                raise ValueError("sh must be a contiguous float32 CUDA tensor of shape [n, 16, 3]")
+            check("dbs_preprocess_gaussian_sh", self.lib.dbs_preprocess_gaussian_sh(
+                C.byref(sp), C.c_void_p(sh.data_ptr()), self.cams_c, self.V, C.byref(self.cfg_c),
+                C.c_void_p(self.projected.data_ptr()), self.projected.numel(),
+                C.c_void_p(self.counts.data_ptr()), _stream()))
+            return
         check("dbs_preprocess", self.lib.dbs_preprocess(
             C.byref(sp), self.cams_c, self.V, C.byref(self.cfg_c), C.c_void_p(self.projected.data_ptr()),
             self.projected.numel(), C.c_void_p(self.counts.data_ptr()), _stream()))

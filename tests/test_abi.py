@@ -63,9 +63,20 @@ def test_host_only_queries(lib):
     # decomposition modes: exclusive pairs are rejected, single modes accepted
     for flags, ok in ((_lib.FLAG_DIFFUSE_ONLY, True), (_lib.FLAG_B_ABOVE | _lib.FLAG_SPECULAR_ONLY, True),
                       (_lib.FLAG_DIFFUSE_ONLY | _lib.FLAG_SPECULAR_ONLY, False),
-                      (_lib.FLAG_B_BELOW | _lib.FLAG_B_ABOVE, False), (32, False)):
+                      (_lib.FLAG_B_BELOW | _lib.FLAG_B_ABOVE, False), (64, False),
+                      (_lib.FLAG_GAUSSIAN_SH, True), (_lib.FLAG_GAUSSIAN_SH | _lib.FLAG_DIFFUSE_ONLY, False),
+                      (_lib.FLAG_GAUSSIAN_SH | _lib.FLAG_B_BELOW, False)):
         c2 = _lib.RasterCfg(16, 16, 256, 1e-4, 0.99, _lib.FLAG_PERSISTENT | flags, 0.5)
         assert (lib.dbs_bins_bytes(10, cams, 2, C.byref(c2)) > 0) == ok, flags
+    # the Gaussian + SH comparison mode: its own preprocess, which needs the flag and the coefficients
+    gcfg = _lib.RasterCfg(16, 16, 256, 1e-4, 0.99, _lib.FLAG_PERSISTENT | _lib.FLAG_GAUSSIAN_SH, 0.0)
+    sp = _lib.Splats(*([None] * 9), 10, 0)
+    assert lib.dbs_preprocess_gaussian_sh(C.byref(sp), None, cams, 2, C.byref(gcfg), None, 0, None, None) \
+        == _lib.ERR_INVALID_ARGUMENT
+    sp = _lib.Splats(*([None] * 9), 0, 0)
+    assert lib.dbs_preprocess_gaussian_sh(C.byref(sp), None, cams, 2, C.byref(cfg), None, 0, None, None) \
+        == _lib.ERR_INVALID_ARGUMENT
+    assert lib.dbs_preprocess(C.byref(sp), cams, 2, C.byref(gcfg), None, 0, None, None) == _lib.ERR_INVALID_ARGUMENT
     c2 = _lib.RasterCfg(16, 16, 256, 1e-4, 0.99, _lib.FLAG_PERSISTENT, float("nan"))
     assert lib.dbs_bins_bytes(10, cams, 2, C.byref(c2)) == 0
     # loss and MCMC entry points validate before touching a device

@@ -1,5 +1,7 @@
 """HIP path vs the CPU FP64 oracle: projection, binning (bit-exact), forward
 images (1e-5), gradients, edge cases.  Needs an MI355X."""
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -211,6 +213,32 @@ def test_elongated_splats_forward_and_backward(oracle):
             g_ref[k] = g_ref[k] + g[k]
             a_ref[k] = a_ref[k] + a[k]
     assert_grads_close(out["grads"], g_ref, a_ref)
+
+
+@pytest.mark.parametrize("tile,batch,persistent", [((16, 16), 256, True), ((8, 8), 64, False)])
+def test_gaussian_sh_comparison_mode_forward(oracle, tile, batch, persistent):
+    """Gaussian kernel cut at 3 sigma + degree-3 SH colour through the same
+    pipeline, against the oracle's comparison mode; the reverse calls and the
+    Beta-path preprocess reject the mode."""
+    from paper_2501_18630_amd import _lib, renderer
+    s = scenes.gaussian_sh(tiny_scene(300, 37, m=2), seed=8, scale_factor=0.5)
+    cams = [scenes.look_at_camera([1.0, 0.5, -5.0], 61, 47, background=(0.3, 0.2, 0.1)),
+            scenes.look_at_camera([-2.5, 1.0, -4.0], 40, 33)]
+    rc = renderer.RasterConfig(tile_w=tile[0], tile_h=tile[1], batch=batch, persistent=persistent,
+                               kernel="gaussian_sh")
+    out = gpu_render(s, cams, rc)
+    for v, cam in enumerate(cams):
+        ref = oracle_view(oracle, s, cam)
+        assert np.count_nonzero(ref["T"] < 0.999) > 200
+        assert_image_close(hw3(out["images"][v]), ref["rgb"], ref["T"], ref["T_prev"])
+    rast, params = out["rast"], out["params"]
+    with pytest.raises(_lib.DbsError):
+        rast.render_bwd(params, out["image_t"], out["T_t"], out["last_t"],
+                        {k: params[k].clone() for k in PARAMS})
+    sp = renderer._splats_c(params, rast.n, rast.m)
+    st = rast.lib.dbs_preprocess(C.byref(sp), rast.cams_c, rast.V, C.byref(rast.cfg_c),
+                                 C.c_void_p(rast.projected.data_ptr()), rast.projected.numel(), None, None)
+    assert st == 1   # DBS_ERR_INVALID_ARGUMENT: the mode needs the SH coefficients
 
 
 def test_forward_deterministic_and_batched_equals_per_view(oracle):
