@@ -144,3 +144,21 @@ def test_config4_sampled_pixels(oracle):
         ref = oracle.render(s, cam, float(AMAX), float(TEPS), pixels=pix)
         gpu = out["images"][v][:, pix[:, 1], pix[:, 0]].T
         assert_image_close(gpu, ref["rgb"], ref["T"], ref["T_prev"])
+
+
+def test_fullsize_gaussian_sh_sampled_pixels(oracle, config3):
+    """The Gaussian + SH comparison mode at config 3's size, as the benchmark
+    runs it (same scales: 3-sigma supports, ~340 M pairs); sampled pixels of
+    two views against the oracle's comparison mode."""
+    from gpu_helpers import gpu_render
+    from paper_2501_18630_amd import renderer
+    s, cams = config3
+    g = scenes.gaussian_sh(s, seed=7, scale_factor=1.0)
+    out = gpu_render(g, cams, renderer.RasterConfig(kernel="gaussian_sh"))
+    rng = np.random.default_rng(13)
+    for v in (0, 15):
+        cam = cams[v]
+        pix = _pixels(rng, cam["width"], cam["height"], 32)
+        ref = oracle.render(g, cam, float(AMAX), float(TEPS), pixels=pix)
+        gpu = out["images"][v][:, pix[:, 1], pix[:, 0]].T
+        assert_image_close(gpu, ref["rgb"], ref["T"], ref["T_prev"])
