@@ -137,6 +137,13 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
             lbeta[mm] = 4.0f * expf(sp.lobe_betas[l]);
         }
 
+        // SH coefficients held in registers across the views (read once per splat)
+        float shc[GSH ? 48 : 1];
+        if (GSH) {
+#pragma unroll
+            for (int k = 0; k < 48; ++k) shc[k] = sh[i * 48 + k];
+        }
+
         uint64_t vm = 0;
         for (int32_t v = 0; v < n_views; ++v) {
             const ViewDesc &V = P.views[v];
@@ -205,13 +212,12 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
                         if (GSH) {
                             float Y[16];
                             sh_basis3(dx, dy, dz, Y);
-                            const float *c = sh + i * 48;
                             cr = cg = cb = 0.5f;
 #pragma unroll
                             for (int k = 0; k < 16; ++k) {
-                                cr = __fmaf_rn(Y[k], c[3 * k], cr);
-                                cg = __fmaf_rn(Y[k], c[3 * k + 1], cg);
-                                cb = __fmaf_rn(Y[k], c[3 * k + 2], cb);
+                                cr = __fmaf_rn(Y[k], shc[3 * k], cr);
+                                cg = __fmaf_rn(Y[k], shc[3 * k + 1], cg);
+                                cb = __fmaf_rn(Y[k], shc[3 * k + 2], cb);
                             }
                             cr = fmaxf(cr, 0.0f);
                             cg = fmaxf(cg, 0.0f);
