@@ -241,6 +241,23 @@ def test_gaussian_sh_comparison_mode_forward(oracle, tile, batch, persistent):
     assert st == 1   # DBS_ERR_INVALID_ARGUMENT: the mode needs the SH coefficients
 
 
+def test_gaussian_sh_batched_equals_per_view():
+    """The comparison mode's batched forward equals its per-view forward, bit
+    for bit, and repeats exactly."""
+    from paper_2501_18630_amd import renderer
+    s = scenes.gaussian_sh(tiny_scene(500, 41, m=0), seed=9, scale_factor=0.6)
+    cams = [scenes.look_at_camera(p, w, h) for p, (w, h) in
+            zip([[0, 0, -6.0], [3.0, 1.0, -5.0], [-2.0, 2.0, -4.0]], [(64, 48), (40, 40), (33, 65)])]
+    rc = renderer.RasterConfig(kernel="gaussian_sh")
+    a = gpu_render(s, cams, rc)
+    b = gpu_render(s, cams, rc)
+    for v in range(3):
+        np.testing.assert_array_equal(a["images"][v], b["images"][v])
+        single = gpu_render(s, [cams[v]], rc)
+        np.testing.assert_array_equal(a["images"][v], single["images"][0])
+        np.testing.assert_array_equal(a["T"][v], single["T"][0])
+
+
 def test_forward_deterministic_and_batched_equals_per_view(oracle):
     s = tiny_scene(800, 11, m=2)
     cams = [scenes.look_at_camera(p, w, h) for p, (w, h) in
