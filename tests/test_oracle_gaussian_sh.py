@@ -39,7 +39,9 @@ def _axis_splat(o, s, z, dc, bg):
                  lobe_colors=np.zeros((1, 0, 3), np.float32), lobe_betas=np.zeros((1, 0), np.float32))
     sh = np.zeros((1, 16, 3), np.float32)
     sh[0, 0] = dc
-    sh[0, 5] = 0.3   # Y_2^-1 = -c yz vanishes on the axis (the view direction is +z)
+    sh[0, 2] = 0.25   # Y_1^0(+z) = sqrt(3 / (4 pi)): odd in the view direction
+    sh[0, 12] = -0.2  # Y_3^0(+z) = sqrt(7 / (4 pi))
+    sh[0, 5] = 0.3    # Y_2^-1 = -c yz vanishes on the axis (the view direction is +z)
     scene["sh"] = sh
     return scene
 
@@ -47,14 +49,17 @@ def _axis_splat(o, s, z, dc, bg):
 def test_gaussian_footprint_closed_form():
     # isotropic splat of scale s at depth z on the optical axis: Sigma' =
     # (f s / z)^2 I, alpha = o exp(-m^2 / 2) with m = |pixel - centre| z / (f s),
-    # zero from m = 3 on; colour = max(0, dc Y_0^0 + 1/2) on the axis
+    # zero from m = 3 on; colour = max(0, dc Y_0^0 + 0.25 Y_1^0 - 0.2 Y_3^0 + 1/2)
+    # with the view direction +z (camera at the origin, splat ahead)
     o, s, z, f, W, H = 0.7, 0.2, 4.0, 40.0, 23, 19
     dc = np.float32([0.8, -0.4, -3.0])
     bg = np.float32([0.1, 0.2, 0.3])
     scene = _axis_splat(o, s, z, dc, bg)
     cam = scenes.camera(W, H, f=f, background=bg)
     out = oracle.render(scene, cam, 0.99, 1e-4)
-    col = np.maximum(dc.astype(np.float64) * 0.5 / np.sqrt(np.pi) + 0.5, 0.0)
+    col = np.maximum(dc.astype(np.float64) * 0.5 / np.sqrt(np.pi)
+                     + np.float64(np.float32(0.25)) * np.sqrt(3.0 / (4.0 * np.pi))
+                     + np.float64(np.float32(-0.2)) * np.sqrt(7.0 / (4.0 * np.pi)) + 0.5, 0.0)
     yy, xx = np.mgrid[0:H, 0:W]
     d2 = (xx + 0.5 - W / 2.0) ** 2 + (yy + 0.5 - H / 2.0) ** 2
     m2 = d2 * (z / (f * np.float64(np.float32(s)))) ** 2

@@ -33,6 +33,8 @@ MUTANTS = {
     "gaussian_extent": ("double ext = s->sh ? 3.0 : 1.0;", "double ext = s->sh ? 2.0 : 1.0;"),
     "sh_legendre_phase": ("case 21: return -3.0 * x * s;", "case 21: return 3.0 * x * s;"),
     "sh_offset": ("double acc = 0.5;", "double acc = 0.0;"),
+    "view_direction_sign": ("double v[3] = {mu[0] - campos[0], mu[1] - campos[1], mu[2] - campos[2]};",
+                            "double v[3] = {campos[0] - mu[0], campos[1] - mu[1], campos[2] - mu[2]};"),
     "quaternion_sign": ("R[1] = 2.0 * (x * y - w * z);", "R[1] = 2.0 * (x * y + w * z);"),
     "termination_rule": ("        last = i;\n        if (T < t_eps) break;",
                          "        last = i;\n        if (T_prev * (1.0 - a) < t_eps * 0.5) break;"),
