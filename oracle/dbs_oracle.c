@@ -26,7 +26,8 @@
  *   - quaternion order (w, x, y, z), normalised before use; scales and
  *     opacity are passed already activated; b and b_m are raw;
  *   - a splat is culled when t_z <= near or det(Sigma') <= 0;
- *   - lobe direction R_m = (sin th cos ph, sin th sin ph, cos th);
+ *   - lobe direction R_m = (sin th cos ph, sin th sin ph, cos th) (parity
+ *     unpinned: the paper prints no example that fixes this convention);
  *     V = (mu - camera centre)/|mu - camera centre|;
  *   - depth order: ascending fp32-rounded t_z, ties by splat index;
  *   - alpha = min(alpha_max, o B(r^2; b)); a splat takes part iff r^2 < 1;
