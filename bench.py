@@ -108,8 +108,6 @@ def stage_times(rast, step, steps):
     acc = {k: 0.0 for k in names}
     for _ in range(steps):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-        for g in step.grads.values():
-            g.zero_()
         ev[0].record()
         rast.preprocess(step.params)
         ev[1].record()
@@ -121,7 +119,7 @@ def stage_times(rast, step, steps):
         ev[4].record()
         rast.raster_bwd(step.dL, step.final_T, step.last)
         ev[5].record()
-        rast.project_bwd(step.params, step.grads)
+        rast.project_bwd(step.params, step.grads, store=True)   # as the step runs it
         ev[6].record()
         torch.cuda.synchronize()
         for k, name in enumerate(names):

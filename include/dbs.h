@@ -80,7 +80,8 @@ typedef struct {
 
 /* Gradients with the same shapes as dbs_splats, FP32.  dbs_render_bwd ADDS
  * into them (+=), so gradients accumulate across calls and views; the caller
- * zeroes them when it wants a fresh gradient. */
+ * zeroes them when it wants a fresh gradient, or sets DBS_FLAG_GRAD_STORE to
+ * have them overwritten. */
 typedef struct {
     float *means, *scales, *quats, *opacities, *betas, *diffuse;
     float *lobe_angles, *lobe_colors, *lobe_betas;
@@ -136,6 +137,13 @@ typedef struct {
  * the reverse calls reject the flag, and it cannot be combined with the
  * decomposition flags. */
 #define DBS_FLAG_GAUSSIAN_SH 32u
+
+/* Gradient store: dbs_project_bwd (and so dbs_render_bwd) writes the
+ * gradients into `grads` instead of adding them, so the caller need not
+ * clear the buffers first (every element of every splat is written; zero for
+ * a splat no view sees).  Without it the gradients accumulate (+=).  The
+ * other calls ignore it. */
+#define DBS_FLAG_GRAD_STORE 64u
 
 /* Fills *cfg with the defaults above (16x16 tiles, batch 256, persistent, no
  * decomposition). */

@@ -21,6 +21,7 @@ FLAG_SPECULAR_ONLY = 4
 FLAG_B_BELOW = 8
 FLAG_B_ABOVE = 16
 FLAG_GAUSSIAN_SH = 32
+FLAG_GRAD_STORE = 64
 
 PARAMS = ("means", "scales", "quats", "opacities", "betas", "diffuse",
           "lobe_angles", "lobe_colors", "lobe_betas")

@@ -40,9 +40,10 @@ static dbs_status check_cfg(const dbs_raster_cfg *cfg)
     if (!(cfg->alpha_max > 0.0f && cfg->alpha_max < 1.0f)) return DBS_ERR_INVALID_ARGUMENT;
     if (!(cfg->t_eps >= 0.0f && cfg->t_eps < 1.0f)) return DBS_ERR_INVALID_ARGUMENT;
     const uint32_t known = DBS_FLAG_PERSISTENT | DBS_FLAG_DIFFUSE_ONLY | DBS_FLAG_SPECULAR_ONLY | DBS_FLAG_B_BELOW |
-                           DBS_FLAG_B_ABOVE | DBS_FLAG_GAUSSIAN_SH;
+                           DBS_FLAG_B_ABOVE | DBS_FLAG_GAUSSIAN_SH | DBS_FLAG_GRAD_STORE;
     if ((cfg->flags & ~known) != 0) return DBS_ERR_INVALID_ARGUMENT;
-    if ((cfg->flags & DBS_FLAG_GAUSSIAN_SH) && (cfg->flags & ~(DBS_FLAG_GAUSSIAN_SH | DBS_FLAG_PERSISTENT)))
+    if ((cfg->flags & DBS_FLAG_GAUSSIAN_SH) &&
+        (cfg->flags & ~(DBS_FLAG_GAUSSIAN_SH | DBS_FLAG_PERSISTENT | DBS_FLAG_GRAD_STORE)))
         return DBS_ERR_INVALID_ARGUMENT;
     if ((cfg->flags & DBS_FLAG_DIFFUSE_ONLY) && (cfg->flags & DBS_FLAG_SPECULAR_ONLY)) return DBS_ERR_INVALID_ARGUMENT;
     if ((cfg->flags & DBS_FLAG_B_BELOW) && (cfg->flags & DBS_FLAG_B_ABOVE)) return DBS_ERR_INVALID_ARGUMENT;
@@ -264,7 +265,8 @@ dbs_status dbs_project_bwd(const dbs_splats *splats, const void *projected, cons
     g.means = grads->means; g.scales = grads->scales; g.quats = grads->quats; g.opacities = grads->opacities;
     g.betas = grads->betas; g.diffuse = grads->diffuse; g.lobe_angles = grads->lobe_angles;
     g.lobe_colors = grads->lobe_colors; g.lobe_betas = grads->lobe_betas;
-    return hip_status(launch_project_bwd(splat_ptrs(splats), P, n_views, g, (hipStream_t)stream));
+    return hip_status(launch_project_bwd(splat_ptrs(splats), P, n_views, g, (cfg->flags & DBS_FLAG_GRAD_STORE) != 0,
+                                         (hipStream_t)stream));
 }
 
 dbs_status dbs_render_bwd(const dbs_splats *splats, const void *projected, const void *bins, const dbs_camera *cams,

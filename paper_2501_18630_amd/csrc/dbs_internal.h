@@ -247,7 +247,8 @@ hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t 
                                const dbs_raster_cfg &cfg, const float *final_T, const int32_t *last_index,
                                int64_t *out, hipStream_t s);
 // project_bwd.hip (also the L1 loss)
-hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, const GradPtrs &g,
+// store: write the gradients instead of adding them to the buffers
+hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, const GradPtrs &g, bool store,
                               hipStream_t s);
 hipError_t launch_l1_loss(const float *image, const float *target, int64_t count, float scale,
                           float *grad, float *loss, hipStream_t s);

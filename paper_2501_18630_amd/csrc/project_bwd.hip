@@ -33,8 +33,10 @@ __device__ __forceinline__ bool line_is_zero(const float4 a, const float4 b, con
 }
 
 // Geometry: dL/dmu' (2), dL/dA (3), dL/do, dL/db  ->  mu, s, q, o, b.  FP64.
+// store: write the gradients instead of adding them (every splat is written,
+// zeros for a splat that no view sees).
 __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
-                                                                   GradPtrs g)
+                                                                   GradPtrs g, int store)
 {
     const int64_t n = sp.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -155,7 +157,18 @@ __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp,
                            dJ12 * (2.0 * fy * ty * iz3) - ga.x * fx * tx * iz2 - ga.y * fy * ty * iz2;
         for (int k = 0; k < 3; ++k) gmu[k] += W[k] * dt0 + W[3 + k] * dt1 + W[6 + k] * dt2;
     }
-    if (!any) return;
+    if (!any) {
+        if (store) {
+            for (int k = 0; k < 3; ++k) {
+                g.means[3 * i + k] = 0.0f;
+                g.scales[3 * i + k] = 0.0f;
+            }
+            for (int k = 0; k < 4; ++k) g.quats[4 * i + k] = 0.0f;
+            g.opacities[i] = 0.0f;
+            g.betas[i] = 0.0f;
+        }
+        return;
+    }
 
     // Sigma = R diag(s^2) R^T  ->  s and the normalised quaternion
     const double w = qv[0], x = qv[1], y = qv[2], z = qv[3];
@@ -182,13 +195,30 @@ __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp,
     dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] - 2.0 * y * dR[8]);
     dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] + y * dR[7]);
     const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+    float out[12];
     for (int k = 0; k < 3; ++k) {
-        g.means[3 * i + k] += (float)gmu[k];
-        g.scales[3 * i + k] += (float)gs[k];
+        out[k] = (float)gmu[k];
+        out[3 + k] = (float)gs[k];
     }
-    for (int k = 0; k < 4; ++k) g.quats[4 * i + k] += (float)((dq[k] - qv[k] * qd) * iqn);
-    g.opacities[i] += (float)go;
-    g.betas[i] += (float)gb;
+    for (int k = 0; k < 4; ++k) out[6 + k] = (float)((dq[k] - qv[k] * qd) * iqn);
+    out[10] = (float)go;
+    out[11] = (float)gb;
+    if (!store) {  // accumulate
+        for (int k = 0; k < 3; ++k) {
+            out[k] += g.means[3 * i + k];
+            out[3 + k] += g.scales[3 * i + k];
+        }
+        for (int k = 0; k < 4; ++k) out[6 + k] += g.quats[4 * i + k];
+        out[10] += g.opacities[i];
+        out[11] += g.betas[i];
+    }
+    for (int k = 0; k < 3; ++k) {
+        g.means[3 * i + k] = out[k];
+        g.scales[3 * i + k] = out[3 + k];
+    }
+    for (int k = 0; k < 4; ++k) g.quats[4 * i + k] = out[6 + k];
+    g.opacities[i] = out[10];
+    g.betas[i] = out[11];
 }
 
 // Colour (Sec. 3.3, Eq. 8): dL/dcolour -> c0, lobes (theta, phi, c_m, b_m) and
@@ -229,7 +259,7 @@ __device__ __forceinline__ float lobe_log2(double d)
 
 template <int M>
 __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
-                                                                GradPtrs g)
+                                                                GradPtrs g, int store)
 {
     const int64_t n = sp.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -320,18 +350,42 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
         const double vdot = aV[0] * Vd[0] + aV[1] * Vd[1] + aV[2] * Vd[2];
         for (int k = 0; k < 3; ++k) gmu[k] += (float)((aV[k] - Vd[k] * vdot) * ivl);
     }
-    if (!any) return;
-    for (int k = 0; k < 3; ++k) {
-        g.means[3 * i + k] += gmu[k];
-        g.diffuse[3 * i + k] += gc0[k];
-    }
+    if (!any) {
+        if (store) {  // the geometry kernel has stored the means' zeros
+            for (int k = 0; k < 3; ++k) g.diffuse[3 * i + k] = 0.0f;
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int64_t l = i * M + m;
-        g.lobe_angles[2 * l] += gth[m];
-        g.lobe_angles[2 * l + 1] += gph[m];
-        for (int c = 0; c < 3; ++c) g.lobe_colors[3 * l + c] += gcm[m][c];
-        g.lobe_betas[l] += gbm[m];
+            for (int m = 0; m < M; ++m) {
+                const int64_t l = i * M + m;
+                g.lobe_angles[2 * l] = 0.0f;
+                g.lobe_angles[2 * l + 1] = 0.0f;
+                for (int c = 0; c < 3; ++c) g.lobe_colors[3 * l + c] = 0.0f;
+                g.lobe_betas[l] = 0.0f;
+            }
+        }
+        return;
+    }
+    // the means always add: the geometry kernel has written its part
+    for (int k = 0; k < 3; ++k) g.means[3 * i + k] += gmu[k];
+    if (store) {
+        for (int k = 0; k < 3; ++k) g.diffuse[3 * i + k] = gc0[k];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int64_t l = i * M + m;
+            g.lobe_angles[2 * l] = gth[m];
+            g.lobe_angles[2 * l + 1] = gph[m];
+            for (int c = 0; c < 3; ++c) g.lobe_colors[3 * l + c] = gcm[m][c];
+            g.lobe_betas[l] = gbm[m];
+        }
+    } else {
+        for (int k = 0; k < 3; ++k) g.diffuse[3 * i + k] += gc0[k];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int64_t l = i * M + m;
+            g.lobe_angles[2 * l] += gth[m];
+            g.lobe_angles[2 * l + 1] += gph[m];
+            for (int c = 0; c < 3; ++c) g.lobe_colors[3 * l + c] += gcm[m][c];
+            g.lobe_betas[l] += gbm[m];
+        }
     }
 }
 
@@ -362,13 +416,15 @@ __global__ void zero_f32_kernel(float *p) { *p = 0.0f; }
 
 }  // namespace
 
-hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, const GradPtrs &g, hipStream_t s)
+hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, const GradPtrs &g, bool store,
+                              hipStream_t s)
 {
     if (sp.n <= 0) return hipSuccess;
     dim3 grid((unsigned)ceil_div(sp.n, 256));
-    project_bwd_geometry_kernel<<<grid, 256, 0, s>>>(sp, P, n_views, g);
+    const int st = store ? 1 : 0;
+    project_bwd_geometry_kernel<<<grid, 256, 0, s>>>(sp, P, n_views, g, st);
     switch (sp.m) {
-#define DBS_PB(MM) case MM: project_bwd_color_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, g); break;
+#define DBS_PB(MM) case MM: project_bwd_color_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, g, st); break;
         DBS_PB(0) DBS_PB(1) DBS_PB(2) DBS_PB(3) DBS_PB(4) DBS_PB(5) DBS_PB(6) DBS_PB(7) DBS_PB(8)
 #undef DBS_PB
         default: return hipErrorInvalidValue;

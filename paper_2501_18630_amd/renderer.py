@@ -100,6 +100,9 @@ class Rasterizer:
         self.n, self.m = int(n), int(m)
         self.cfg = cfg or RasterConfig()
         self.cfg_c = self.cfg.to_c()
+        # the same configuration with the gradient store flag (reverse calls that overwrite)
+        self.cfg_store_c = self.cfg.to_c()
+        self.cfg_store_c.flags |= _lib.FLAG_GRAD_STORE
         self.device = torch.device(device)
         self.headroom = headroom
         self.sizes = [(int(c["height"]), int(c["width"])) for c in self.cams]
@@ -167,12 +170,14 @@ class Rasterizer:
             C.byref(self.cfg_c), self.n, C.c_void_p(image.data_ptr()), C.c_void_p(final_T.data_ptr()),
             C.c_void_p(last.data_ptr()), _stream()))
 
-    def render_bwd(self, params: dict, dL_dimage, final_T, last, grads: dict):
+    def render_bwd(self, params: dict, dL_dimage, final_T, last, grads: dict, store: bool = False):
+        """Gradients added into `grads`, or written over them with store=True."""
         sp = _splats_c(params, self.n, self.m)
         gr = _grads_c(grads)
+        cfg = self.cfg_store_c if store else self.cfg_c
         check("dbs_render_bwd", self.lib.dbs_render_bwd(
             C.byref(sp), C.c_void_p(self.projected.data_ptr()), C.c_void_p(self.bins.data_ptr()),
-            self.cams_c, self.V, C.byref(self.cfg_c), C.c_void_p(final_T.data_ptr()),
+            self.cams_c, self.V, C.byref(cfg), C.c_void_p(final_T.data_ptr()),
             C.c_void_p(last.data_ptr()), C.c_void_p(dL_dimage.data_ptr()), C.byref(gr), _stream()))
 
     def raster_bwd(self, dL_dimage, final_T, last, atomics=None):
@@ -190,11 +195,12 @@ class Rasterizer:
                 C.byref(self.cfg_c), self.n, C.c_void_p(final_T.data_ptr()), C.c_void_p(last.data_ptr()),
                 C.c_void_p(dL_dimage.data_ptr()), C.c_void_p(atomics.data_ptr()), _stream()))
 
-    def project_bwd(self, params: dict, grads: dict):
+    def project_bwd(self, params: dict, grads: dict, store: bool = False):
         sp = _splats_c(params, self.n, self.m)
         gr = _grads_c(grads)
+        cfg = self.cfg_store_c if store else self.cfg_c
         check("dbs_project_bwd", self.lib.dbs_project_bwd(
-            C.byref(sp), C.c_void_p(self.projected.data_ptr()), self.cams_c, self.V, C.byref(self.cfg_c),
+            C.byref(sp), C.c_void_p(self.projected.data_ptr()), self.cams_c, self.V, C.byref(cfg),
             C.byref(gr), _stream()))
 
     def stats(self, final_T, last) -> dict:
@@ -406,9 +412,8 @@ class TrainStep:
             r.l1_loss(self.image, self.target, self.scale, self.dL, self.loss)
         else:
             r.photometric_loss(self.image, self.target, self.lambda_ssim, self.dL, self.loss)
-        for g in self.grads.values():
-            g.zero_()
-        r.render_bwd(self.params, self.dL, self.final_T, self.last, self.grads)
+        # the reverse pass writes every gradient element: no clearing needed
+        r.render_bwd(self.params, self.dL, self.final_T, self.last, self.grads, store=True)
         if self.lambda_o or self.lambda_s:
             r.regularizer(self.params, self.lambda_o, self.lambda_s, self.grads, self.loss)
 

@@ -63,7 +63,7 @@ def test_host_only_queries(lib):
     # decomposition modes: exclusive pairs are rejected, single modes accepted
     for flags, ok in ((_lib.FLAG_DIFFUSE_ONLY, True), (_lib.FLAG_B_ABOVE | _lib.FLAG_SPECULAR_ONLY, True),
                       (_lib.FLAG_DIFFUSE_ONLY | _lib.FLAG_SPECULAR_ONLY, False),
-                      (_lib.FLAG_B_BELOW | _lib.FLAG_B_ABOVE, False), (64, False),
+                      (_lib.FLAG_B_BELOW | _lib.FLAG_B_ABOVE, False), (128, False), (_lib.FLAG_GRAD_STORE, True),
                       (_lib.FLAG_GAUSSIAN_SH, True), (_lib.FLAG_GAUSSIAN_SH | _lib.FLAG_DIFFUSE_ONLY, False),
                       (_lib.FLAG_GAUSSIAN_SH | _lib.FLAG_B_BELOW, False)):
         c2 = _lib.RasterCfg(16, 16, 256, 1e-4, 0.99, _lib.FLAG_PERSISTENT | flags, 0.5)

@@ -311,6 +311,29 @@ def test_backward_matches_oracle(oracle, which):
     assert_grads_close(out["grads"], g_ref, a_ref)
 
 
+def test_backward_gradient_store_overwrites():
+    """DBS_FLAG_GRAD_STORE: the reverse pass writes every gradient element
+    (zeros for splats no view sees) and equals accumulation into zeros, bit
+    for bit, whatever the buffers held before."""
+    import torch
+    s = tiny_scene(150, 43, m=3)
+    s["means"][:20, 2] = -8.0   # behind both cameras: no visible record
+    cams = [scenes.look_at_camera([0.5, 0.5, -6.0], 40, 30), scenes.look_at_camera([2.0, -1.0, -5.0], 33, 29)]
+    dl = _dl(cams, 48)
+    out = gpu_render(s, cams, grads_from=dl)   # accumulated into zeros
+    rast, params = out["rast"], out["params"]
+    dL = torch.cat([torch.as_tensor(g).reshape(-1) for g in dl]).cuda()
+    # a fresh forward leaves the state the reverse pass consumes
+    image, T, last = rast.forward(params)
+    junk = {k: torch.full_like(params[k], float("nan")) for k in PARAMS}
+    rast.render_bwd(params, dL, T, last, junk, store=True)
+    torch.cuda.synchronize()
+    for k in PARAMS:
+        got = junk[k].cpu().numpy().astype(np.float64)
+        np.testing.assert_array_equal(got, out["grads"][k], err_msg=k)
+    assert np.all(junk["means"][:20].cpu().numpy() == 0.0)
+
+
 def test_backward_config1_crop_and_finite_differences(oracle):
     s, cams = scenes.config1()
     cam = cams[0]
