@@ -91,3 +91,16 @@ def test_no_cpu_fallback_when_library_missing(tmp_path):
     from paper_2501_18630_amd import _lib
     with pytest.raises(ImportError):
         _lib.load(str(tmp_path / "missing.so"))
+
+
+def test_raster_config_flags():
+    """Host-side mapping of the Python configuration onto dbs_raster_cfg flags."""
+    from paper_2501_18630_amd import _lib, renderer
+    assert renderer.RasterConfig().to_c().flags == _lib.FLAG_PERSISTENT
+    c = renderer.RasterConfig(kernel="gaussian_sh", persistent=False).to_c()
+    assert c.flags == _lib.FLAG_GAUSSIAN_SH
+    c = renderer.RasterConfig(color="diffuse", b_range="above", b_split=0.25).to_c()
+    assert c.flags == _lib.FLAG_PERSISTENT | _lib.FLAG_DIFFUSE_ONLY | _lib.FLAG_B_ABOVE
+    assert abs(c.b_split - 0.25) < 1e-7
+    with pytest.raises(KeyError):
+        renderer.RasterConfig(kernel="gaussian").to_c()
