@@ -226,8 +226,8 @@ class Rasterizer:
         self.render_fwd(image, final_T, last)
         return image, final_T, last
 
-    def backward(self, params: dict, dL_dimage, final_T, last, grads: dict):
-        self.render_bwd(params, dL_dimage.contiguous(), final_T, last, grads)
+    def backward(self, params: dict, dL_dimage, final_T, last, grads: dict, store: bool = False):
+        self.render_bwd(params, dL_dimage.contiguous(), final_T, last, grads, store=store)
         return grads
 
     def l1_loss(self, image, target, scale: float, dL_dimage, loss=None):
@@ -325,8 +325,8 @@ class _RenderFn(torch.autograd.Function):
         saved = ctx.saved_tensors
         params = dict(zip(PARAMS, saved[:len(PARAMS)]))
         final_T, last = saved[len(PARAMS)], saved[len(PARAMS) + 1]
-        grads = {k: torch.zeros_like(params[k]) for k in PARAMS}
-        ctx.rast.backward(params, g_image.contiguous(), final_T, last, grads)
+        grads = {k: torch.empty_like(params[k]) for k in PARAMS}   # every element is stored
+        ctx.rast.backward(params, g_image.contiguous(), final_T, last, grads, store=True)
         return (None, *[grads[k] for k in PARAMS])
 
 
