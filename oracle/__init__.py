@@ -76,7 +76,9 @@ def _load():
         lib.ob_sh_basis3.argtypes = [P, P]
         lib.ob_project.argtypes = [P, P] + [P] * 10
         lib.ob_render.argtypes = [P, P, C.c_double, C.c_double, C.c_int64, P, P, P, P, P, P]
-        lib.ob_render_bwd.argtypes = [P, P, C.c_double, C.c_double, C.c_int64, P, P, P, P]
+        lib.ob_render_bwd.argtypes = [P, P, C.c_double, C.c_double, C.c_int64, P, P, P, P, P]
+        lib.ob_set_threads.restype = C.c_int
+        lib.ob_set_threads.argtypes = [C.c_int]
         lib.ob_bin.restype = C.c_int64
         lib.ob_bin.argtypes = [C.c_int64, P, P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                C.c_int64, P, P]
@@ -182,24 +184,37 @@ def render(scene: dict, cam: dict, alpha_max: float, t_eps: float, pixels=None) 
 
 
 def render_bwd(scene: dict, cam: dict, alpha_max: float, t_eps: float, dL_drgb, pixels=None,
-               want_abs: bool = False):
+               want_abs: bool = False, want_contrib: bool = False):
     """Gradient of sum_p dL_drgb[p] . rgb[p] w.r.t. every splat parameter.
-    Returns (grads, abs_sums or None); abs_sums[k] is, per parameter, the sum
-    over pixels of |that pixel's contribution|."""
+    Returns (grads, abs_sums or None), or with want_contrib (grads, abs_sums,
+    contrib_sums).  abs_sums[k] is, per parameter, the sum over pixels and
+    screen-space adjoints j of |J_pj| |s_j| (J the chain from the ten
+    screen-space adjoints to the parameters); contrib_sums[k] the sum over
+    pixels of |that pixel's contribution| (never larger)."""
     lib = _load()
     px = _pixels(cam, pixels)
     g_in = np.ascontiguousarray(dL_drgb, np.float64).reshape(px.shape[0], 3)
     s64 = _scene64(scene)
     grads = {k: np.zeros_like(s64[k]) for k in PARAMS}
     absd = {k: np.zeros_like(s64[k]) for k in PARAMS} if want_abs else None
+    con = {k: np.zeros_like(s64[k]) for k in PARAMS} if want_contrib else None
     sp, cm = _splats(s64), _camera(cam)
     gs = _Grads(*[grads[k].ctypes.data for k in PARAMS])
     ab = _Grads(*[absd[k].ctypes.data for k in PARAMS]) if want_abs else None
+    cb = _Grads(*[con[k].ctypes.data for k in PARAMS]) if want_contrib else None
     rc = lib.ob_render_bwd(C.byref(sp), C.byref(cm), float(alpha_max), float(t_eps), px.shape[0],
-                           _ptr(px), _ptr(g_in), C.byref(gs), C.byref(ab) if ab is not None else None)
+                           _ptr(px), _ptr(g_in), C.byref(gs), C.byref(ab) if ab is not None else None,
+                           C.byref(cb) if cb is not None else None)
     if rc != 0:
         raise MemoryError("oracle render_bwd failed")
+    if want_contrib:
+        return grads, absd, con
     return grads, absd
+
+
+def set_threads(n: int) -> int:
+    """Number of host threads the oracle's OpenMP loops use; returns it."""
+    return int(_load().ob_set_threads(int(n)))
 
 
 def bin_pairs(valid, bbox, depth_key, width: int, height: int, tile_w: int, tile_h: int):

@@ -25,7 +25,8 @@
  *   - J is the affine (EWA) Jacobian of the pinhole map at the splat centre;
  *   - quaternion order (w, x, y, z), normalised before use; scales and
  *     opacity are passed already activated; b and b_m are raw;
- *   - a splat is culled when t_z <= near or det(Sigma') <= 0;
+ *   - a splat is culled when t_z <= near or det(Sigma') <= 0, and in every
+ *     view when any of its parameters is not finite (NaN or +-inf);
  *   - lobe direction R_m = (sin th cos ph, sin th sin ph, cos th) (parity
  *     unpinned: the paper prints no example that fixes this convention);
  *     V = (mu - camera centre)/|mu - camera centre|;
@@ -39,6 +40,9 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -160,9 +164,40 @@ typedef struct {
     int32_t bbox[4];       /* x_lo, x_hi, y_lo, y_hi (inclusive) */
 } ob_fwd;
 
+/* 1 when every parameter of splat i is a finite number.  The paper defines
+ * the primitive for real-valued parameters only; a splat with a NaN or
+ * infinite parameter is treated as absent (culled in every view), so that
+ * it neither poisons the image nor receives a gradient. */
+static int params_finite(const ob_splats *s, int64_t i)
+{
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(s->means[3 * i + k]) || !isfinite(s->scales[3 * i + k])) return 0;
+    for (int k = 0; k < 4; ++k)
+        if (!isfinite(s->quats[4 * i + k])) return 0;
+    if (!isfinite(s->opacities[i])) return 0;
+    if (s->sh) {
+        for (int k = 0; k < 48; ++k)
+            if (!isfinite(s->sh[48 * i + k])) return 0;
+        return 1;
+    }
+    if (!isfinite(s->betas[i])) return 0;
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(s->diffuse[3 * i + k])) return 0;
+    for (int64_t k = 0; k < s->m; ++k) {
+        const int64_t l = i * s->m + k;
+        if (!isfinite(s->lobe_angles[2 * l]) || !isfinite(s->lobe_angles[2 * l + 1])) return 0;
+        if (!isfinite(s->lobe_colors[3 * l]) || !isfinite(s->lobe_colors[3 * l + 1]) ||
+            !isfinite(s->lobe_colors[3 * l + 2]))
+            return 0;
+        if (!isfinite(s->lobe_betas[l])) return 0;
+    }
+    return 1;
+}
+
 static void project_one(const ob_splats *s, int64_t i, const ob_camera *cam, ob_fwd *f)
 {
     memset(f, 0, sizeof(*f));
+    if (!params_finite(s, i)) return;
     const double *mu = s->means + 3 * i;
     const double *W = cam->R;
     /* camera-space centre, summed left to right: ((W0 mu0 + W1 mu1) + W2 mu2) + t */
@@ -423,25 +458,19 @@ typedef struct {
     double mean2d[2], G[3], opacity, b, color[3];
 } ob_screen_adj;
 
-static void add_grad(double *g, double *unused, int64_t idx, double v)
-{
-    (void)unused;
-    g[idx] += v;
-}
+static void add_grad(double *g, int64_t idx, double v) { g[idx] += v; }
 
 static void chain_one(const ob_splats *s, int64_t i, const ob_camera *cam, const ob_fwd *f,
                       const ob_screen_adj *sa, ob_grads *g)
 {
     const double *W = cam->R;
     const int m_l = s->m;
-#define AG(field) NULL
-
-    add_grad(g->opacities, AG(opacities), i, sa->opacity);
-    add_grad(g->betas, AG(betas), i, sa->b);
+    add_grad(g->opacities, i, sa->opacity);
+    add_grad(g->betas, i, sa->b);
 
     /* colour -> c0, lobes, and the view direction */
     double adjV[3] = {0.0, 0.0, 0.0};
-    for (int c = 0; c < 3; ++c) add_grad(g->diffuse, AG(diffuse), 3 * i + c, sa->color[c]);
+    for (int c = 0; c < 3; ++c) add_grad(g->diffuse, 3 * i + c, sa->color[c]);
     for (int m = 0; m < m_l; ++m) {
         int64_t lm = i * m_l + m;
         double th = s->lobe_angles[2 * lm], ph = s->lobe_angles[2 * lm + 1];
@@ -453,19 +482,19 @@ static void chain_one(const ob_splats *s, int64_t i, const ob_camera *cam, const
         double w = x > 0.0 ? pow(x, bm) : 0.0;
         double adj_w = 0.0;
         for (int c = 0; c < 3; ++c) {
-            add_grad(g->lobe_colors, AG(lobe_colors), 3 * lm + c, w * sa->color[c]);
+            add_grad(g->lobe_colors, 3 * lm + c, w * sa->color[c]);
             adj_w += sa->color[c] * s->lobe_colors[3 * lm + c];
         }
         if (x > 0.0) {
-            add_grad(g->lobe_betas, AG(lobe_betas), lm, adj_w * w * log(x) * bm);
+            add_grad(g->lobe_betas, lm, adj_w * w * log(x) * bm);
             double adj_x = adj_w * bm * pow(x, bm - 1.0);
-            add_grad(g->lobe_angles, AG(lobe_angles), 2 * lm,
+            add_grad(g->lobe_angles, 2 * lm,
                      adj_x * (dR_dth[0] * f->vdir[0] + dR_dth[1] * f->vdir[1] + dR_dth[2] * f->vdir[2]));
-            add_grad(g->lobe_angles, AG(lobe_angles), 2 * lm + 1,
+            add_grad(g->lobe_angles, 2 * lm + 1,
                      adj_x * (dR_dph[0] * f->vdir[0] + dR_dph[1] * f->vdir[1] + dR_dph[2] * f->vdir[2]));
             for (int k = 0; k < 3; ++k) adjV[k] += adj_x * Rm[k];
         } else {
-            add_grad(g->lobe_betas, AG(lobe_betas), lm, 0.0);
+            add_grad(g->lobe_betas, lm, 0.0);
         }
     }
     /* V = v/|v|, v = mu - campos */
@@ -518,7 +547,7 @@ static void chain_one(const ob_splats *s, int64_t i, const ob_camera *cam, const
     dt[2] += -sa->mean2d[0] * fx * tx / (tz * tz) - sa->mean2d[1] * fy * ty / (tz * tz);
     /* t = W mu + t_v */
     for (int k = 0; k < 3; ++k) gmu[k] += W[k] * dt[0] + W[3 + k] * dt[1] + W[6 + k] * dt[2];
-    for (int k = 0; k < 3; ++k) add_grad(g->means, AG(means), 3 * i + k, gmu[k]);
+    for (int k = 0; k < 3; ++k) add_grad(g->means, 3 * i + k, gmu[k]);
 
     /* Sigma = R diag(s^2) R^T */
     const double *sc = s->scales + 3 * i;
@@ -534,7 +563,7 @@ static void chain_one(const ob_splats *s, int64_t i, const ob_camera *cam, const
         double acc = 0.0;   /* (R^T dSig R)_cc */
         for (int r = 0; r < 3; ++r)
             for (int k = 0; k < 3; ++k) acc += Rq[3 * r + c] * dSig[3 * r + k] * Rq[3 * k + c];
-        add_grad(g->scales, AG(scales), 3 * i + c, 2.0 * sc[c] * acc);
+        add_grad(g->scales, 3 * i + c, 2.0 * sc[c] * acc);
     }
     /* rotation matrix entries as functions of the normalised quaternion */
     double w = f->qn[0], x = f->qn[1], y = f->qn[2], z = f->qn[3];
@@ -545,8 +574,7 @@ static void chain_one(const ob_splats *s, int64_t i, const ob_camera *cam, const
     dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] + y * dR[7]);
     /* q_n = q/|q| */
     double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-    for (int k = 0; k < 4; ++k) add_grad(g->quats, AG(quats), 4 * i + k, (dq[k] - f->qn[k] * qd) / f->qnorm);
-#undef AG
+    for (int k = 0; k < 4; ++k) add_grad(g->quats, 4 * i + k, (dq[k] - f->qn[k] * qd) / f->qnorm);
 }
 
 
@@ -613,10 +641,13 @@ static void splat_jacobian(const ob_splats *s, int64_t i, const ob_camera *cam, 
  * |J_pj| |s_j(pixel)|, with J the Jacobian of the reverse chain from the ten
  * screen-space adjoints of the splat to its parameters: a computation that
  * sums the per-pixel screen-space adjoints in finite precision and then
- * applies the chain has an error bounded by a multiple of it. */
+ * applies the chain has an error bounded by a multiple of it.  abs_contrib
+ * (may be NULL) receives the smaller scale sum over pixels of
+ * |sum_j J_pj s_j(pixel)|, the magnitude of each pixel's own contribution to
+ * the gradient of p. */
 int ob_render_bwd(const ob_splats *s, const ob_camera *cam, double alpha_max, double t_eps,
                   int64_t npix, const int32_t *pix_xy, const double *dL_drgb,
-                  ob_grads *grads, ob_grads *abs_sum)
+                  ob_grads *grads, ob_grads *abs_sum, ob_grads *abs_contrib)
 {
     ob_scene sc;
     if (s->sh) return -2;  /* the comparison mode is forward only */
@@ -627,7 +658,8 @@ int ob_render_bwd(const ob_splats *s, const ob_camera *cam, double alpha_max, do
     double **jac = NULL;
     ob_grads scratch;
     memset(&scratch, 0, sizeof(scratch));
-    if (abs_sum) {
+    const int want_j = abs_sum != NULL || abs_contrib != NULL;
+    if (want_j) {
         size_t n1 = (size_t)(s->n > 0 ? s->n : 1);
         size_t m1 = (size_t)(s->m > 0 ? s->m : 1);
         jac = (double **)calloc(n1, sizeof(double *));
@@ -642,6 +674,7 @@ int ob_render_bwd(const ob_splats *s, const ob_camera *cam, double alpha_max, do
         scratch.lobe_betas = (double *)calloc(n1 * m1, sizeof(double));
     }
     double *absv = (double *)malloc(sizeof(double) * (size_t)q);
+    double *absc = (double *)malloc(sizeof(double) * (size_t)q);
     ob_step *steps = (ob_step *)malloc(sizeof(ob_step) * (size_t)cap * (size_t)chunk);
     int64_t *nsteps = (int64_t *)malloc(sizeof(int64_t) * (size_t)chunk);
     double *Tfin = (double *)malloc(sizeof(double) * (size_t)chunk);
@@ -690,7 +723,7 @@ int ob_render_bwd(const ob_splats *s, const ob_camera *cam, double alpha_max, do
                     sa.mean2d[1] = -adj_r2 * 2.0 * (f->conic[1] * e->dx + f->conic[2] * e->dy);
                 }
                 chain_one(s, e->id, cam, f, &sa, grads);
-                if (abs_sum) {
+                if (want_j) {
                     if (!jac[e->id]) {
                         jac[e->id] = (double *)malloc(sizeof(double) * (size_t)q * 10);
                         splat_jacobian(s, e->id, cam, f, &scratch, jac[e->id]);
@@ -698,16 +731,21 @@ int ob_render_bwd(const ob_splats *s, const ob_camera *cam, double alpha_max, do
                     const double *J = jac[e->id];
                     const double *sv = (const double *)&sa;
                     for (int pp2 = 0; pp2 < q; ++pp2) {
-                        double acc = 0.0;
-                        for (int j = 0; j < 10; ++j) acc += fabs(J[pp2 * 10 + j]) * fabs(sv[j]);
+                        double acc = 0.0, con = 0.0;
+                        for (int j = 0; j < 10; ++j) {
+                            acc += fabs(J[pp2 * 10 + j]) * fabs(sv[j]);
+                            con += J[pp2 * 10 + j] * sv[j];
+                        }
                         absv[pp2] = acc;
+                        absc[pp2] = fabs(con);
                     }
-                    splat_params_add(abs_sum, e->id, s->m, absv);
+                    if (abs_sum) splat_params_add(abs_sum, e->id, s->m, absv);
+                    if (abs_contrib) splat_params_add(abs_contrib, e->id, s->m, absc);
                 }
             }
         }
     }
-    if (abs_sum) {
+    if (want_j) {
         for (int64_t i = 0; i < s->n; ++i) free(jac[i]);
         free(jac);
         free(scratch.means); free(scratch.scales); free(scratch.quats); free(scratch.opacities);
@@ -715,9 +753,23 @@ int ob_render_bwd(const ob_splats *s, const ob_camera *cam, double alpha_max, do
         free(scratch.lobe_betas);
     }
     free(absv);
+    free(absc);
     free(steps); free(nsteps); free(Tfin);
     scene_free(&sc);
     return 0;
+}
+
+/* Threads the OpenMP loops use (n >= 1); returns the resulting maximum.  For
+ * timing the oracle on a chosen number of host cores. */
+int ob_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */

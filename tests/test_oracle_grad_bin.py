@@ -92,6 +92,25 @@ def test_error_scale_bounds_the_gradient(oracle):
     assert (g["diffuse"] != 0).any()
 
 
+def test_contribution_scale_between_gradient_and_error_scale(oracle):
+    """The per-pixel contribution scale sum_pixels |contribution| lies
+    between |gradient| and the error scale sum_pixels sum_j |J_pj| |s_j|, and
+    equals |gradient| for a single pixel."""
+    cam = scenes.look_at_camera((1.0, 1.0, -4.0), 16, 16)
+    s = fd_scene(7, n=3)
+    w = np.random.default_rng(2).standard_normal((256, 3))
+    g, a, c = oracle.render_bwd(s, cam, AMAX, 0.0, w, want_abs=True, want_contrib=True)
+    for k in PARAMS:
+        assert np.all(c[k] >= np.abs(g[k]) * (1 - 1e-12)), k
+        assert np.all(c[k] <= a[k] * (1 + 1e-12)), k
+    assert any((c[k] > np.abs(g[k]) * (1 + 1e-6)).any() for k in PARAMS)   # pixels cancel somewhere
+    pix = np.array([[8, 8]])
+    g, a, c = oracle.render_bwd(s, cam, AMAX, 0.0, np.array([[0.3, -0.7, 1.1]]), pixels=pix, want_abs=True,
+                                want_contrib=True)
+    for k in PARAMS:
+        np.testing.assert_allclose(c[k], np.abs(g[k]), rtol=1e-9, atol=1e-300)
+
+
 # ---------------------------------------------------------------- binning
 
 def test_binning_matches_pixel_enumeration(oracle):

@@ -228,3 +228,56 @@ def test_spherical_beta_view_direction_from_camera_to_splat(oracle):
     p = oracle.project(one_splat([6.0, 0.0, -2.0], [.1] * 3, c0=(0, 0, 0),
                                  lobes=[(np.pi - th, np.pi, (1, 1, 1), 0.0)]), cam)
     np.testing.assert_allclose(p["color"][0], [0, 0, 0], atol=1e-15)
+
+
+# ---------------------------------------------------------------- non-finite parameters
+
+def _three_splats():
+    """Three overlapping splats in front of a camera at the origin looking
+    along +z, two lobes each, tilted 0.5 rad from the view direction (so the
+    lobe factors lie strictly inside (0, 1))."""
+    rows = [([0.02, 0.01, 3.0], 0.9), ([-0.05, 0.03, 3.2], 1.1), ([0.04, -0.04, 3.4], 1.3)]
+    n, m = 3, 2
+    s = dict(means=np.array([r[0] for r in rows], np.float64),
+             scales=np.array([[0.3, 0.25, 0.2]] * n, np.float64),
+             quats=np.array([[0.9, 0.1, -0.2, 0.3]] * n, np.float64),
+             opacities=np.array([0.6, 0.5, 0.7], np.float64),
+             betas=np.array([0.1, -0.2, 0.3], np.float64),
+             diffuse=np.array([[0.2, 0.4, 0.6], [0.5, 0.1, 0.3], [0.3, 0.3, 0.3]], np.float64),
+             lobe_angles=np.array([[[0.5, 0.0], [0.5, 1.5]]] * n, np.float64),
+             lobe_colors=np.full((n, m, 3), 0.3), lobe_betas=np.array([[0.2, -0.3]] * n, np.float64))
+    return s
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_non_finite_parameters_cull_the_splat(oracle, bad):
+    """A splat with any non-finite parameter is treated as absent in every
+    view: projection invalid, image and every other splat's gradient exactly
+    those of the scene without it, its own gradient zero."""
+    cam = scenes.camera(32, 32, f=32.0, background=(0.1, 0.2, 0.3))
+    base = _three_splats()
+    keep = [0, 2]
+    ref_img = oracle.render(scenes.subset(base, keep), cam, AMAX_NF, TEPS_NF)["rgb"]
+    w = np.random.default_rng(8).standard_normal((32 * 32, 3))
+    ref_g, _ = oracle.render_bwd(scenes.subset(base, keep), cam, AMAX_NF, TEPS_NF, w)
+    full_img = oracle.render(base, cam, AMAX_NF, TEPS_NF)["rgb"]
+    assert np.abs(full_img - ref_img).max() > 1e-3       # splat 1 matters when finite
+    cases = 0
+    for k in PARAM_KEYS:
+        for j in range(base[k].reshape(3, -1).shape[1]):
+            s = {kk: v.copy() for kk, v in base.items()}
+            s[k].reshape(3, -1)[1, j] = bad
+            assert oracle.project(s, cam)["valid"].tolist() == [1, 0, 1], (k, j)
+            img = oracle.render(s, cam, AMAX_NF, TEPS_NF)["rgb"]
+            np.testing.assert_array_equal(img, ref_img, err_msg=f"{k}[{j}]")
+            g, _ = oracle.render_bwd(s, cam, AMAX_NF, TEPS_NF, w)
+            for kk in PARAM_KEYS:
+                np.testing.assert_array_equal(g[kk][keep], ref_g[kk], err_msg=f"{k}[{j}] -> {kk}")
+                assert not np.any(g[kk][1]), (k, j, kk)
+            cases += 1
+    assert cases == 3 + 3 + 4 + 1 + 1 + 3 + 4 + 6 + 2
+
+
+AMAX_NF, TEPS_NF = float(np.float32(0.99)), float(np.float32(1e-4))
+PARAM_KEYS = ("means", "scales", "quats", "opacities", "betas", "diffuse",
+              "lobe_angles", "lobe_colors", "lobe_betas")

@@ -38,8 +38,10 @@ MUTANTS = {
     "quaternion_sign": ("R[1] = 2.0 * (x * y - w * z);", "R[1] = 2.0 * (x * y + w * z);"),
     "termination_rule": ("        last = i;\n        if (T < t_eps) break;",
                          "        last = i;\n        if (T_prev * (1.0 - a) < t_eps * 0.5) break;"),
-    "scale_adjoint_factor": ("add_grad(g->scales, AG(scales), 3 * i + c, 2.0 * sc[c] * acc);",
-                             "add_grad(g->scales, AG(scales), 3 * i + c, sc[c] * acc);"),
+    "scale_adjoint_factor": ("add_grad(g->scales, 3 * i + c, 2.0 * sc[c] * acc);",
+                             "add_grad(g->scales, 3 * i + c, sc[c] * acc);"),
+    "non_finite_not_culled": ("    if (!params_finite(s, i)) return;\n", ""),
+    "lobe_beta_not_checked": ("        if (!isfinite(s->lobe_betas[l])) return 0;\n", ""),
 }
 
 
