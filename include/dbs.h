@@ -36,6 +36,15 @@
  *     with a non-positive projected-covariance determinant, are culled.
  *   - Every buffer that `dbs_*_bytes` sizes must stay untouched by the caller
  *     between the calls that use it.
+ *   - The splat count n, the views and the tile shape (cfg->tile_w, tile_h)
+ *     given to dbs_bin_sort, dbs_render_fwd, dbs_render_bwd, dbs_raster_bwd,
+ *     dbs_project_bwd and dbs_render_stats must be the ones the last
+ *     dbs_preprocess on the same `projected` used (and, for the raster calls,
+ *     the last dbs_bin_sort on the same `bins`).  The buffers record what
+ *     they were built for: dbs_bin_sort reports a mismatch with *overflow = 2
+ *     and lists nothing, and the other calls then do nothing on the device
+ *     (their outputs keep their previous contents) instead of reading the
+ *     buffers with another layout.
  */
 #ifndef DBS_H
 #define DBS_H
@@ -70,7 +79,13 @@ typedef enum {
  *   lobe_angles  [n,m,2] (theta, phi): R_m = (sin th cos ph, sin th sin ph, cos th)
  *   lobe_colors  [n,m,3] c_m
  *   lobe_betas   [n,m]  raw b_m; the lobe exponent is 4 e^{b_m}
- * Lobe pointers may be NULL when m = 0. */
+ * Lobe pointers may be NULL when m = 0.
+ * The primitive is defined for real parameters: a splat with a NaN or
+ * infinite value in any of its parameters is culled in every view (it
+ * contributes to no pixel and receives zero gradient).  The exponents
+ * 4 e^b and 4 e^{b_m} are evaluated in FP32 and held at the largest finite
+ * float (b above about 87.3), so the kernel stays 1 at r^2 = 0 and 0 inside
+ * the rest of the support. */
 typedef struct {
     const float *means, *scales, *quats, *opacities, *betas, *diffuse;
     const float *lobe_angles, *lobe_colors, *lobe_betas;
@@ -200,9 +215,11 @@ dbs_status dbs_preprocess_gaussian_sh(const dbs_splats *splats /*[host] struct o
 
 /* Tile lists (Sec. 3.2, sorting by depth before Eq. 6): every visible record
  * is listed in each tile its pixel box overlaps; each list is ordered by the
- * fp32 bits of the camera-space depth, ties by splat index.  If the number
- * of pairs exceeds pair_capacity, *overflow (device int32) is set to 1 and
- * every tile list is left empty; otherwise *overflow is set to 0. */
+ * fp32 bits of the camera-space depth, ties by splat index.  *overflow
+ * (device int32) is set to 1 if the number of pairs exceeds pair_capacity,
+ * to 2 if `projected` was written by a dbs_preprocess with another n,
+ * n_views or tile shape (its pair count does not hold for this call), and
+ * to 0 otherwise; in both error cases every tile list is left empty. */
 dbs_status dbs_bin_sort(const void *projected, const dbs_camera *cams /*[host]*/, int32_t n_views,
                         const dbs_raster_cfg *cfg /*[host]*/, int64_t n,
                         int64_t pair_capacity, void *bins, size_t bins_bytes,
@@ -376,7 +393,7 @@ dbs_status dbs_bins_layout(void *bins, int64_t pair_capacity, const dbs_camera *
 
 const char *dbs_status_string(dbs_status s);
 
-/* Library version, e.g. "dbs 0.1 gfx950". */
+/* Library version, e.g. "dbs 0.2 gfx950". */
 const char *dbs_version(void);
 
 #ifdef __cplusplus

@@ -291,7 +291,7 @@ dbs_status dbs_render_stats(const void *projected, const void *bins, const dbs_c
     const int64_t n_tiles = total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h);
     ProjPtrs P = proj_ptrs((void *)projected, n, n_views);
     BinsPtrs B = bins_ptrs((void *)bins, n_tiles);
-    return hip_status(launch_raster_stats(P, B, n_views, n_tiles, *cfg, final_T, last_index, out,
+    return hip_status(launch_raster_stats(P, B, n, n_views, n_tiles, *cfg, final_T, last_index, out,
                                           (hipStream_t)stream));
 }
 
@@ -410,6 +410,6 @@ const char *dbs_status_string(dbs_status s)
     return "unknown status";
 }
 
-const char *dbs_version(void) { return "dbs 0.1 gfx950"; }
+const char *dbs_version(void) { return "dbs 0.2 gfx950"; }
 
 }  // extern "C"

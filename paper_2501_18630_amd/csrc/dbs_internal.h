@@ -48,13 +48,19 @@ struct ProjHeader {
 static_assert(sizeof(ProjHeader) == 128, "ProjHeader layout");
 
 // Header at the start of `bins`.
+// overflow: 0 = binned, 1 = pair capacity exceeded, 2 = `projected` was
+// written for another splat count, view count or tile shape (every list is
+// left empty in both error cases).
 struct BinsHeader {
     int32_t overflow;
     uint32_t n_vis;        // visible records
     uint32_t n_pairs;      // pairs actually binned (0 on overflow)
     uint32_t n_tiles;
     uint32_t queue[4];     // persistent work queues: fwd head, fwd done, bwd head, bwd done
-    uint32_t pad[24];
+    uint32_t n_rec;        // records the compaction reads: n * n_views, 0 on a mismatch
+    int32_t n_views, tile_w, tile_h;
+    int64_t n;             // what the lists were built for
+    uint32_t pad[18];
 };
 static_assert(sizeof(BinsHeader) == 128, "BinsHeader layout");
 
@@ -243,7 +249,7 @@ hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
                              const dbs_raster_cfg &cfg, const float *final_T,
                              const int32_t *last_index, const float *dL_dimage, float *sgrad, int64_t *atomics,
                              hipStream_t s);
-hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t n_tiles,
+hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views, int64_t n_tiles,
                                const dbs_raster_cfg &cfg, const float *final_T, const int32_t *last_index,
                                int64_t *out, hipStream_t s);
 // project_bwd.hip (also the L1 loss)

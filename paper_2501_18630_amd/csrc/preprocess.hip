@@ -45,6 +45,11 @@ __global__ void upload_views_kernel(ViewUpload up, ViewDesc *views, ProjHeader *
     }
 }
 
+__device__ __forceinline__ bool finite3(float a, float b, float c)
+{
+    return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
 __device__ inline uint64_t wave_sum_u64(uint64_t v)
 {
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
@@ -95,6 +100,14 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
         double q0 = sp.quats[4 * i], q1 = sp.quats[4 * i + 1], q2 = sp.quats[4 * i + 2],
                q3 = sp.quats[4 * i + 3];
         double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        // The primitive is defined for real-valued parameters: a splat with a
+        // NaN or infinite parameter is absent from every view (culled here, so
+        // it neither reaches the image nor receives a gradient).  The centre's
+        // coordinates are tested through their FP64 sum, which no finite FP32
+        // values can overflow.
+        bool fin = isfinite(qn) && isfinite(mu[0] + mu[1] + mu[2]) &&
+                   finite3(sp.scales[3 * i], sp.scales[3 * i + 1], sp.scales[3 * i + 2]) &&
+                   isfinite(sp.opacities[i]);
         bool ok = qn > 0.0;
         // geometry decomposition: primitives outside the b range are culled in every view
         if (flags & DBS_FLAG_B_BELOW) ok = ok && sp.betas[i] < b_split;
@@ -119,10 +132,20 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
                 Sig[b][a] = acc;
             }
         const float opac = sp.opacities[i];
-        const float beta = GSH ? 0.0f : 4.0f * expf(sp.betas[i]);
+        // beta = 4 e^b, held below FP32 overflow so that (1 - r^2)^beta stays
+        // defined (1 at r^2 = 0, 0 elsewhere) for very large b
+        const float beta = GSH ? 0.0f : fminf(4.0f * expf(sp.betas[i]), 3.4028235e38f);
         const bool c0_on = diffuse_on && !GSH;
-        const float c0r = c0_on ? sp.diffuse[3 * i] : 0.0f, c0g = c0_on ? sp.diffuse[3 * i + 1] : 0.0f,
-                    c0b = c0_on ? sp.diffuse[3 * i + 2] : 0.0f;
+        float c0r = 0.0f, c0g = 0.0f, c0b = 0.0f;
+        if (!GSH) {
+            const float d0 = sp.diffuse[3 * i], d1 = sp.diffuse[3 * i + 1], d2 = sp.diffuse[3 * i + 2];
+            fin = fin && isfinite(sp.betas[i]) && finite3(d0, d1, d2);
+            if (c0_on) {
+                c0r = d0;
+                c0g = d1;
+                c0b = d2;
+            }
+        }
         float lr[M > 0 ? M : 1][3], lc[M > 0 ? M : 1][3], lbeta[M > 0 ? M : 1];
 #pragma unroll
         for (int mm = 0; mm < M; ++mm) {
@@ -134,7 +157,9 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
             lr[mm][1] = st * sph;
             lr[mm][2] = ct;
             for (int c = 0; c < 3; ++c) lc[mm][c] = sp.lobe_colors[3 * l + c];
-            lbeta[mm] = 4.0f * expf(sp.lobe_betas[l]);
+            lbeta[mm] = fminf(4.0f * expf(sp.lobe_betas[l]), 3.4028235e38f);
+            fin = fin && finite3(sp.lobe_angles[2 * l], sp.lobe_angles[2 * l + 1], sp.lobe_betas[l]) &&
+                  finite3(lc[mm][0], lc[mm][1], lc[mm][2]);
         }
 
         // SH coefficients held in registers across the views (read once per splat)
@@ -142,7 +167,12 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
         if (GSH) {
 #pragma unroll
             for (int k = 0; k < 48; ++k) shc[k] = sh[i * 48 + k];
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 48; ++k) acc += 0.0f * shc[k];  // NaN iff some coefficient is NaN or infinite
+            fin = fin && acc == 0.0f;
         }
+        ok = ok && fin;
 
         uint64_t vm = 0;
         for (int32_t v = 0; v < n_views; ++v) {

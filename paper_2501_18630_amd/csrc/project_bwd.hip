@@ -5,7 +5,12 @@
 // conic (A00, A01, A11 as full-matrix entries), dL/do, dL/db, dL/dcolour (3).
 // Each line is cleared after it is read, so the accumulator is zero again
 // for the next reverse pass.  Output: dL/dparameter for every parameter of
-// Sec. 3.2 Eq. (4) and Sec. 3.3 Eq. (8), ADDED to the caller's buffers.
+// Sec. 3.2 Eq. (4) and Sec. 3.3 Eq. (8), added to the caller's buffers, or,
+// in store mode (DBS_FLAG_GRAD_STORE), written over them: every element of
+// every splat is then written, zero for a splat no view sees.  In store mode
+// the geometry kernel stores the means' gradient and the colour kernel then
+// adds its view-direction part to it, so the two launches must run in this
+// order on one stream (they do: both are enqueued by one call).
 //
 // Chain (Sec. 3.2):  A = Sigma'^{-1}  ->  dSigma' = -A G A;
 //   Sigma' = M Sigma M^T, M = J W  ->  dSigma = M^T dSigma' M, dM = 2 dSigma' M Sigma;
@@ -26,6 +31,13 @@ namespace dbs {
 
 namespace {
 
+// `projected` was laid out for this splat and view count (else its record
+// pointers would not match, and the call leaves everything untouched).
+__device__ __forceinline__ bool proj_matches(const ProjPtrs &P, int64_t n, int32_t n_views)
+{
+    return P.hdr->n == n && P.hdr->n_views == n_views;
+}
+
 __device__ __forceinline__ bool line_is_zero(const float4 a, const float4 b, const float4 c)
 {
     return a.x == 0.f && a.y == 0.f && a.z == 0.f && a.w == 0.f && b.x == 0.f && b.y == 0.f && b.z == 0.f &&
@@ -40,7 +52,7 @@ __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp,
 {
     const int64_t n = sp.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || !proj_matches(P, n, n_views)) return;
 
     const double mu[3] = {sp.means[3 * i], sp.means[3 * i + 1], sp.means[3 * i + 2]};
     double qv[4] = {sp.quats[4 * i], sp.quats[4 * i + 1], sp.quats[4 * i + 2], sp.quats[4 * i + 3]};
@@ -263,7 +275,7 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
 {
     const int64_t n = sp.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || !proj_matches(P, n, n_views)) return;
     constexpr int MM = M > 0 ? M : 1;
     const double mu[3] = {sp.means[3 * i], sp.means[3 * i + 1], sp.means[3 * i + 2]};
     double st[MM], ct[MM], sph[MM], cph[MM];
@@ -274,7 +286,7 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
         sincos((double)sp.lobe_angles[2 * l], &st[m], &ct[m]);
         sincos((double)sp.lobe_angles[2 * l + 1], &sph[m], &cph[m]);
         for (int c = 0; c < 3; ++c) lcol[m][c] = sp.lobe_colors[3 * l + c];
-        lbeta[m] = 4.0f * expf(sp.lobe_betas[l]);
+        lbeta[m] = fminf(4.0f * expf(sp.lobe_betas[l]), 3.4028235e38f);  // as in the projection
     }
     float gmu[3] = {0.f, 0.f, 0.f}, gc0[3] = {0.f, 0.f, 0.f};
     float gth[MM], gph[MM], gcm[MM][3], gbm[MM];

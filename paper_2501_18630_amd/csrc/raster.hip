@@ -40,6 +40,9 @@ namespace dbs {
 namespace {
 
 struct RasterArgs {
+    const ProjHeader *ph;
+    const BinsHeader *bh;
+    int64_t n;
     const ViewDesc *views;
     int32_t n_views;
     uint32_t n_tiles;
@@ -75,6 +78,15 @@ __device__ __forceinline__ float eval_kernel(float omr, float beta, float *lg)
     return __builtin_amdgcn_exp2f(__fmul_rn(beta, *lg));
 }
 
+// alpha = min(alpha_max, o B), with the same clamp decision in both passes:
+// a product that is not at most alpha_max (NaN included) is clamped, takes
+// alpha_max and passes no gradient to o, b or the geometry.
+__device__ __forceinline__ float clamp_alpha(float araw, float alpha_max, bool *clamped)
+{
+    *clamped = !(araw <= alpha_max);
+    return *clamped ? alpha_max : araw;
+}
+
 __device__ __forceinline__ float2 unpack2(double d) { return __builtin_bit_cast(float2, d); }
 __device__ __forceinline__ double pack2(float a, float b) { return __builtin_bit_cast(double, make_float2(a, b)); }
 
@@ -86,6 +98,17 @@ __device__ __forceinline__ int find_view(const ViewDesc *views, int32_t n_views,
         if ((uint32_t)views[mid].tile_offset <= g) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// The buffers were built for this splat count, view count and tile shape:
+// otherwise the pointers derived from them would not match the buffers'
+// layout, and the raster calls leave everything untouched.
+template <int TW, int TH>
+__device__ __forceinline__ bool buffers_match(const RasterArgs &a)
+{
+    const BinsHeader *bh = a.bh;
+    return bh->n == a.n && bh->n_views == a.n_views && bh->tile_w == TW && bh->tile_h == TH &&
+           bh->n_tiles == a.n_tiles && a.ph->n == a.n && a.ph->n_views == a.n_views;
 }
 
 struct Item {
@@ -100,7 +123,8 @@ __device__ __forceinline__ bool fetch_item(const RasterArgs &a, uint32_t *head, 
 {
     if (threadIdx.x == 0) {
         uint32_t k;
-        if (a.persistent) k = atomicAdd(head, 1u);
+        if (iter == 0 && !buffers_match<TW, TH>(a)) k = a.n_tiles;
+        else if (a.persistent) k = atomicAdd(head, 1u);
         else k = iter == 0 ? blockIdx.x : a.n_tiles;
         Item it;
         it.g = 0xffffffffu;
@@ -409,7 +433,8 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                     float lg;
                     const float B = GAUSS ? __builtin_amdgcn_exp2f(-6.4921276840003350f * (float)r2)
                                           : eval_kernel((float)(1.0 - r2), ob.y, &lg);
-                    const float alpha = fminf(a.alpha_max, __fmul_rn(ob.x, B));
+                    bool clamped;
+                    const float alpha = clamp_alpha(__fmul_rn(ob.x, B), a.alpha_max, &clamped);
                     const float wgt = alpha * T;
                     const float4 cc = s_col[k];
                     C0 = __fmaf_rn(cc.x, wgt, C0);
@@ -569,8 +594,9 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                     float lg;
                     const float B = eval_kernel(omr, ob.y, &lg);
                     const float araw = __fmul_rn(ob.x, B);
-                    const bool clamped = araw > a.alpha_max;
-                    const float alpha = contrib ? (clamped ? a.alpha_max : araw) : 0.0f;
+                    bool clamped;
+                    const float alpha_c = clamp_alpha(araw, a.alpha_max, &clamped);
+                    const float alpha = contrib ? alpha_c : 0.0f;
                     const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
                     const float Ti = T * inv;
                     const float wgt = alpha * Ti;
@@ -660,6 +686,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
 template <int TW, int TH>
 __global__ __launch_bounds__(TW *TH) void raster_stats_kernel(RasterArgs a, int64_t *out)
 {
+    if (!buffers_match<TW, TH>(a)) return;
     const uint32_t g = blockIdx.x;
     const int v = find_view(a.views, a.n_views, g);
     const ViewDesc &V = a.views[v];
@@ -713,6 +740,7 @@ __global__ __launch_bounds__(TW *TH) void raster_wave_stats_kernel(RasterArgs a,
     const LanePixel<TW, TH> P(w, lane);
     const double fpx = (double)P.lx + 0.5, fpy = (double)P.ly + 0.5;
     const uint8_t *my_row = &s_rows[w][P.row * BATCH];
+    if (!buffers_match<TW, TH>(a)) return;  // uniform
     const uint32_t g = blockIdx.x;
     const int v = find_view(a.views, a.n_views, g);
     const ViewDesc &V = a.views[v];
@@ -826,9 +854,13 @@ int persistent_grid(void *kernel, int threads)
     return g;
 }
 
-RasterArgs make_args(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t n_tiles, const dbs_raster_cfg &cfg)
+RasterArgs make_args(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views, int64_t n_tiles,
+                     const dbs_raster_cfg &cfg)
 {
     RasterArgs a{};
+    a.ph = P.hdr;
+    a.bh = B.hdr;
+    a.n = n;
     a.views = P.views;
     a.n_views = n_views;
     a.n_tiles = (uint32_t)n_tiles;
@@ -862,10 +894,9 @@ hipError_t launch_raster_fwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
                              const dbs_raster_cfg &cfg, float *image, float *final_T, int32_t *last_index,
                              hipStream_t s)
 {
-    (void)n;
     const Entry *e = find_entry(cfg.tile_w, cfg.tile_h, cfg.batch);
     if (!e) return hipErrorInvalidValue;
-    RasterArgs a = make_args(P, B, n_views, n_tiles, cfg);
+    RasterArgs a = make_args(P, B, n, n_views, n_tiles, cfg);
     a.image = image;
     a.final_T = final_T;
     a.last_index = last_index;
@@ -877,10 +908,9 @@ hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
                              const dbs_raster_cfg &cfg, const float *final_T, const int32_t *last_index,
                              const float *dL_dimage, float *sgrad, int64_t *atomics, hipStream_t s)
 {
-    (void)n;
     const Entry *e = find_entry(cfg.tile_w, cfg.tile_h, cfg.batch);
     if (!e) return hipErrorInvalidValue;
-    RasterArgs a = make_args(P, B, n_views, n_tiles, cfg);
+    RasterArgs a = make_args(P, B, n, n_views, n_tiles, cfg);
     a.final_T = (float *)final_T;
     a.last_index = (int32_t *)last_index;
     a.dL_dimage = dL_dimage;
@@ -891,11 +921,12 @@ hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
 
 bool raster_supported(int tw, int th, int batch) { return find_entry(tw, th, batch) != nullptr; }
 
-hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t n_tiles, const dbs_raster_cfg &cfg,
-                               const float *final_T, const int32_t *last_index, int64_t *out, hipStream_t s)
+hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views, int64_t n_tiles,
+                               const dbs_raster_cfg &cfg, const float *final_T, const int32_t *last_index,
+                               int64_t *out, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
-    RasterArgs a = make_args(P, B, n_views, n_tiles, cfg);
+    RasterArgs a = make_args(P, B, n, n_views, n_tiles, cfg);
     a.final_T = (float *)final_T;
     a.last_index = (int32_t *)last_index;
     const int tw = cfg.tile_w, th = cfg.tile_h;
@@ -910,7 +941,6 @@ hipError_t launch_raster_stats(ProjPtrs P, BinsPtrs B, int32_t n_views, int64_t 
     DBS_STATS(16, 16) DBS_STATS(16, 8) DBS_STATS(8, 8) DBS_STATS(32, 8) DBS_STATS(32, 16)
 #undef DBS_STATS
     return hipErrorInvalidValue;
-    return hipGetLastError();
 }
 
 }  // namespace dbs

@@ -415,16 +415,26 @@ hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Co
 
 // ---------------------------------------------------------------- binning kernels
 
-__global__ void finalize_counts_kernel(const ProjHeader *ph, BinsHeader *bh, int64_t cap, uint32_t n_tiles,
-                                       int32_t *overflow_out)
+// The pair count was taken by the preprocess with its tile shape: binning
+// with another shape, splat count or view count would emit a different
+// number of pairs than the capacity check saw, so such a call bins nothing
+// (overflow 2), as does a count above the capacity (overflow 1).
+__global__ void finalize_counts_kernel(const ProjHeader *ph, BinsHeader *bh, int64_t n, int32_t n_views, int tw,
+                                       int th, int64_t cap, uint32_t n_tiles, int32_t *overflow_out)
 {
     if (threadIdx.x != 0) return;
+    const bool match = ph->n == n && ph->n_views == n_views && ph->tile_w == tw && ph->tile_h == th;
     const int64_t vis = ph->counts[0], pairs = ph->counts[1];
-    const int32_t ovf = pairs > cap ? 1 : 0;
+    const int32_t ovf = !match ? 2 : (pairs > cap ? 1 : 0);
     bh->overflow = ovf;
-    bh->n_vis = (uint32_t)vis;
+    bh->n_rec = match ? (uint32_t)(n * n_views) : 0u;
+    bh->n_vis = match ? (uint32_t)vis : 0u;
     bh->n_pairs = ovf ? 0u : (uint32_t)pairs;
     bh->n_tiles = n_tiles;
+    bh->n_views = n_views;
+    bh->tile_w = tw;
+    bh->tile_h = th;
+    bh->n = n;
     for (int k = 0; k < 4; ++k) bh->queue[k] = 0;
     if (overflow_out) *overflow_out = ovf;
 }
@@ -465,6 +475,7 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, c
                                                          const ViewDesc *views, uint32_t n, int tw, int th,
                                                          uint32_t *pkeys, uint32_t *pvals)
 {
+    // pairs are only emitted below n_pairs (at most the capacity)
     __shared__ uint32_t s_off[257];
     __shared__ uint32_t s_rec[256], s_row0[256], s_tx[256];
     __shared__ uint16_t s_w[256];
@@ -487,9 +498,11 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, c
         if (t == cntb - 1) s_off[cntb] = off + (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
     }
     __syncthreads();
-    const uint32_t base = s_off[0], total = s_off[cntb] - base;
+    const uint32_t base = s_off[0], cap = bh->n_pairs;
+    const uint32_t total = s_off[cntb] - base;
     for (uint32_t p = t; p < total; p += 256) {
         const uint32_t gp = base + p;
+        if (gp >= cap) break;
         int lo = 0, hi = cntb - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -576,11 +589,12 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     const int64_t R = n * n_views;
     hipError_t e;
 
-    finalize_counts_kernel<<<1, 64, 0, s>>>(P.hdr, B.hdr, cap, (uint32_t)n_tiles, overflow_out);
+    finalize_counts_kernel<<<1, 64, 0, s>>>(P.hdr, B.hdr, n, n_views, tile_w, tile_h, cap, (uint32_t)n_tiles,
+                                            overflow_out);
 
     // 1. compact visible records, then sort them by depth bits
     if (R > 0) {
-        e = device_scan(LoadVisible{P.ntiles}, StoreCompact{P.depth, keys_a, vals_a}, Count{nullptr, R},
+        e = device_scan(LoadVisible{P.ntiles}, StoreCompact{P.depth, keys_a, vals_a}, Count{&B.hdr->n_rec, R},
                         partials, s);
         if (e != hipSuccess) return e;
     }
