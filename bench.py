@@ -2,11 +2,14 @@
 batched multi-view (one call per stage, replayed from a HIP graph) vs per-view
 (the same calls once per view, eager).
 
-    python bench.py [--steps K] [--warmup W] [--config 3] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--repeats R] [--config 3] [--no-cpu-baseline]
 
 A step is one training iteration of the whole hot path over every view:
 preprocess -> bin/sort -> forward -> L1 loss gradient -> backward (gradients
 of every splat parameter).  Inputs are resident in HBM before timing starts.
+`value` comes from K steps timed together; the step-time distribution
+(median, p10, p90) from R more replays timed one by one with HIP events, and
+the forward-only rate from R replays of a graph of the forward half.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -23,14 +26,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published (packed FP32, an FMA counted as 2)
+# The same chip without packed FP32 (which this build does not issue): 256 CUs
+# x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-operations/s, 78.6 TFLOP/s with
+# an FMA counted as 2.
+LANE_OPS_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 
-# Algorithmic FP32 operations (an FMA counts 2, a transcendental 1) per
-# (pixel, pair), counted from the arithmetic the method needs:
-#   support test r^2 = d^T A d of every evaluated pair ............... 9
-#   forward compositing of a pair with r^2 < 1 (Eq. 6) ............... 15
-#   reverse pass of a pair with r^2 < 1, including its share of the
-#   per-splat sums over pixels (10 values) ........................... 68
+# Algorithmic operations per (pixel, pair) of the reverse raster pass, two
+# counting conventions:
+#  - per operation (each add, multiply, FMA, compare or transcendental is 1):
+#    6 for a support test that rejects the pair (r^2 >= 1), 47 for a pair
+#    with r^2 < 1 (its test, the reverse arithmetic of Eq. 6 with two
+#    transcendentals, and its share of the ten per-splat sums);
+#  - FLOP with an FMA counted as 2: 9 per support test (evaluated pair) and
+#    68 more per pair with r^2 < 1.
+OPS_BWD_REJECT = 6
+OPS_BWD_CONTRIB = 47
 FLOP_TEST = 9
 FLOP_FWD_CONTRIB = 15
 FLOP_BWD_CONTRIB = 68
@@ -77,16 +88,22 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--repeats", type=int, default=50,
+                    help="graph replays timed one by one with HIP events for the step-time distribution")
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--tile", default="auto", help="WxH, or auto (autotuned, outside the timed region)")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-pixels", type=int, default=3072)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only copy a 1 GiB buffer (reference for HBM byte counters) and exit")
+    ap.add_argument("--cpu-sample-pixels", type=int, default=2048)
+    ap.add_argument("--cpu-sample-pixels-1t", type=int, default=128)
+    ap.add_argument("--step-only", action="store_true",
+                    help="only the batched step (warm-up, then K timed steps): the run profiled with counters")
+    ap.add_argument("--copy-calibration", choices=["full", "half-lines"], default=None,
+                    help="only copy a buffer and exit (reference for the HBM byte counters): 'full' copies "
+                         "1 GiB; 'half-lines' reads the first 32 bytes of every 64-byte line of 1 GiB")
     return ap.parse_args()
 
 
@@ -98,6 +115,46 @@ def timed(fn, steps):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def step_distribution(fn, repeats):
+    """Per-step milliseconds of `repeats` calls, each bracketed by HIP events
+    on torch's current stream (the stream the graph replays on)."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(repeats + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for k in range(repeats):
+        fn()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(repeats)])
+    return {"n": repeats, "median_ms": round(float(np.median(ms)), 4),
+            "p10_ms": round(float(np.percentile(ms, 10)), 4), "p90_ms": round(float(np.percentile(ms, 90)), 4),
+            "min_ms": round(float(ms.min()), 4), "max_ms": round(float(ms.max()), 4)}
+
+
+def forward_graph(rast, params):
+    """preprocess -> bin/sort -> forward of every view, captured in one HIP
+    graph (the rendering half of the step, comparable in kind to a frame
+    render time)."""
+    import torch
+    outputs = rast.new_outputs()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        rast.preprocess(params)
+        rast.bin_sort()
+        rast.render_fwd(*outputs)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rast.preprocess(params)
+        rast.bin_sort()
+        rast.render_fwd(*outputs)
+    torch.cuda.synchronize()
+    return g, outputs
 
 
 def stage_times(rast, step, steps):
@@ -239,25 +296,47 @@ def atomic_count(rast, step):
     return int(cnt.item())
 
 
-def cpu_baseline(scene, cams, n_pixels: int, seed: int = 5):
-    """The oracle, as it is, on a bounded sample: fwd + bwd of `n_pixels`
-    random pixels of the first view (every splat of the scene is projected
-    and depth-sorted for that view, then each sampled pixel is composited by
-    brute force over all of them)."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scene, cams, n_pixels: int, n_pixels_1t: int, seed: int = 5):
+    """The oracle, as it is, on bounded samples: fwd + bwd of random pixels of
+    the first view (every splat of the scene is projected and depth-sorted for
+    that view, then each sampled pixel is composited by brute force over all
+    of them), on all the host threads OpenMP is given and on one thread."""
     import oracle
     cam = cams[0]
     rng = np.random.default_rng(seed)
-    pix = np.stack([rng.integers(0, cam["width"], n_pixels), rng.integers(0, cam["height"], n_pixels)], 1)
-    dl = rng.standard_normal((n_pixels, 3))
     amax, teps = float(np.float32(0.99)), float(np.float32(1e-4))
-    t0 = time.perf_counter()
-    oracle.render(scene, cam, amax, teps, pixels=pix)
-    oracle.render_bwd(scene, cam, amax, teps, dl, pixels=pix)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    s64 = {k: np.ascontiguousarray(v, np.float64) for k, v in scene.items()}
+
+    def run(k):
+        pix = np.stack([rng.integers(0, cam["width"], k), rng.integers(0, cam["height"], k)], 1)
+        dl = rng.standard_normal((k, 3))
+        t0 = time.perf_counter()
+        oracle.render(s64, cam, amax, teps, pixels=pix)
+        oracle.render_bwd(s64, cam, amax, teps, dl, pixels=pix)
+        return time.perf_counter() - t0
+
+    want = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.set_threads(want)
+    dt = run(n_pixels)
+    oracle.set_threads(1)
+    dt1 = run(n_pixels_1t)
+    oracle.set_threads(cores)
+    where = f"random pixels of view 0 ({cam['width']}x{cam['height']}) over all {scene['means'].shape[0]} splats"
     return {"value": n_pixels / dt / 1e6, "unit": "Mpix/s", "cores": cores, "kind": "oracle",
-            "sample": f"fwd+bwd of {n_pixels} random pixels of view 0 ({cam['width']}x{cam['height']}) over "
-                      f"all {scene['means'].shape[0]} splats, {dt:.1f} s"}
+            "sample": f"fwd+bwd of {n_pixels} {where}, {dt:.1f} s on {cores} threads",
+            "single_thread": {"value": n_pixels_1t / dt1 / 1e6, "unit": "Mpix/s", "cores": 1,
+                              "sample": f"fwd+bwd of {n_pixels_1t} {where}, {dt1:.1f} s"},
+            "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()}}
 
 
 def main():
@@ -271,10 +350,18 @@ def main():
 
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
+        if args.copy_calibration == "full":
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            moved = {"read_bytes": src.numel() * 4, "write_bytes": src.numel() * 4}
+        else:
+            half = src.view(-1, 16)[:, :8]   # 32 B of each 64 B line
+            dst = torch.empty(half.shape, dtype=torch.float32, device="cuda")
+            dst.copy_(half)
+            moved = {"read_bytes": half.numel() * 4, "lines_touched_bytes": src.numel() * 4,
+                     "write_bytes": dst.numel() * 4}
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 4}))
+        print(json.dumps({"copy_calibration": args.copy_calibration, **moved}))
         return
 
     t0 = time.perf_counter()
@@ -304,8 +391,22 @@ def main():
     torch.cuda.reset_peak_memory_stats()
     t_batched = timed(step.run, args.steps)
     peak_mem = torch.cuda.max_memory_allocated()
+    free_b, total_b = torch.cuda.mem_get_info()   # hipMemGetInfo, with every buffer of the step held
     assert not step.overflowed()
     log(f"batched: {t_batched * 1e3:.3f} ms/step")
+    if args.step_only:
+        print(json.dumps({"ms_per_step": round(t_batched * 1e3, 4), "steps": args.steps,
+                          "config": f"config{args.config}, tile {tw}x{th}, batch {cfg.batch}"}), flush=True)
+        return
+    dist = step_distribution(step.run, args.repeats)
+    log(f"batched step over {args.repeats} replays: {dist}")
+    fwd_g, fwd_out = forward_graph(rast, params)
+    for _ in range(args.warmup):
+        fwd_g.replay()
+    fwd_dist = step_distribution(fwd_g.replay, args.repeats)
+    assert int(rast.overflow.item()) == 0
+    log(f"batched forward over {args.repeats} replays: {fwd_dist}")
+    del fwd_g, fwd_out
 
     per_view = None
     if not args.no_per_view:
@@ -349,8 +450,10 @@ def main():
     # dominant kernel: the raster reverse pass; ALU-bound (support tests plus
     # the reverse arithmetic of contributing pairs), priced against FP32 peak
     bwd_flops = wc["bwd_evaluated"] * FLOP_TEST + wc["contributing"] * FLOP_BWD_CONTRIB
+    bwd_ops = (wc["bwd_evaluated"] - wc["contributing"]) * OPS_BWD_REJECT + wc["contributing"] * OPS_BWD_CONTRIB
     t_bwd = st["raster_bwd"] * 1e-3
-    achieved = bwd_flops / t_bwd / 1e12
+    achieved = bwd_ops / t_bwd / 1e12
+    achieved_flop = bwd_flops / t_bwd / 1e12
     fwd_flops = wc["fwd_evaluated"] * FLOP_TEST + wc["contributing"] * FLOP_FWD_CONTRIB
     result = {
         "metric": "fwd+bwd Mpix/s, batched vs per-view, 1 MI355X, img err<=1e-5 vs FP64",
@@ -369,14 +472,30 @@ def main():
                                f"{m} lobes, tile {tw}x{th}, batch {cfg.batch}"
                                f"{' (autotuned)' if args.tile == 'auto' else ''}, batched + hipGraph",
                    "views": len(cams), "pixels": X, "splats": n, "lobes": m},
+        "step_ms": dist,
+        "forward": {"value": round(X / (fwd_dist["median_ms"] * 1e-3) / 1e6, 3), "unit": "Mpix/s",
+                    "ms": fwd_dist, "what": "preprocess -> bin/sort -> raster forward of every view, one HIP graph"},
         "peak_device_memory_GiB": round(peak_mem / 2**30, 2),
+        "device_memory_used_GiB": round((total_b - free_b) / 2**30, 2),
         "per_view_value": round(per_view, 3) if per_view else None,
         "batched_speedup": round(mpix / per_view, 3) if per_view else None,
         "roofline": {"kernel": "raster_bwd_kernel", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                      "traffic": measured_traffic(f"config {args.config}, tile {tw}x{th}, batch {cfg.batch}"),
-                     "flops_per_launch": bwd_flops, "ms_per_launch": round(st["raster_bwd"], 4)},
+                     "ms_per_launch": round(st["raster_bwd"], 4),
+                     "counting": f"{OPS_BWD_REJECT} operations per rejected support test, {OPS_BWD_CONTRIB} per "
+                                 "pair with r^2 < 1 (each add, multiply, FMA, compare or transcendental is one)",
+                     "ops_per_launch": bwd_ops,
+                     "peak_basis": "published FP32 vector peak (packed FP32, FMA = 2)",
+                     "frac_of_issue_peak": round(achieved / LANE_OPS_PEAK_T, 4),
+                     "issue_peak": {"value": round(LANE_OPS_PEAK_T, 2), "unit": "T lane-ops/s",
+                                    "basis": "non-packed FP32 issue: 256 CUs x 64 lanes x 2.4 GHz"},
+                     "flop_count": {"flops_per_launch": bwd_flops, "achieved_TFLOPs": round(achieved_flop, 3),
+                                    "counting": f"FMA = 2: {FLOP_TEST} per support test, {FLOP_BWD_CONTRIB} more "
+                                                "per pair with r^2 < 1",
+                                    "frac_of_157.3": round(achieved_flop / FP32_VECTOR_PEAK_TFLOPS, 4),
+                                    "frac_of_78.6_non_packed": round(achieved_flop / (2 * LANE_OPS_PEAK_T), 4)}},
         "step_hbm": {"algorithmic_bytes": sb, "achieved_GBs": round(sb / t_batched / 1e9, 1),
                      "peak_GBs": HBM_PEAK_GBS, "frac": round(sb / t_batched / 1e9 / HBM_PEAK_GBS, 4)},
         "raster_fwd_tflops": round(fwd_flops / (st["raster_fwd"] * 1e-3) / 1e12, 3),
@@ -393,7 +512,7 @@ def main():
                            "bytes_added": 4 * n_atomics},
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(scene, cams, args.cpu_sample_pixels)
+        result["cpu_baseline"] = cpu_baseline(scene, cams, args.cpu_sample_pixels, args.cpu_sample_pixels_1t)
     print(json.dumps(result), flush=True)
 
 

@@ -6,8 +6,9 @@ built (tile_w, tile_h, batch), then re-times the few fastest with more steps,
 in alternating order, and keeps the fastest of those.  A warm-up run of the
 first shape precedes the sweep so that the first shapes timed are not
 charged for clock ramp-up.  Results are cached in a
-JSON file keyed by the GPU architecture, the view resolutions and the splat
-and lobe counts, so a workload is tuned once per machine type.
+JSON file keyed by the GPU architecture, the HIP runtime and library
+versions, the view resolutions and the splat and lobe counts, so a workload
+is tuned once per machine type and software stack.
 
     cfg = autotune.tune(cams, params, target)      # RasterConfig
 """
@@ -28,9 +29,13 @@ CACHE = os.environ.get("DBS_AUTOTUNE_CACHE",
 
 
 def workload_key(cams, n: int, m: int) -> str:
+    """GPU architecture, HIP runtime and library versions (a new compiler or
+    kernel build can move the optimum), splat and lobe counts, resolutions."""
+    from . import _lib
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
     res = ",".join(f"{c['width']}x{c['height']}" for c in cams)
-    return f"{arch}|{n}|{m}|{res}"
+    lib = _lib.load().dbs_version().decode()
+    return f"{arch}|hip {torch.version.hip}|{lib}|{n}|{m}|{res}"
 
 
 def _load_cache(path: str) -> dict:
