@@ -226,6 +226,24 @@ dbs_status dbs_bin_sort(const void *projected, const dbs_camera *cams /*[host]*/
                         void *workspace, size_t workspace_bytes,
                         int32_t *overflow /* device int32 or NULL */, void *stream);
 
+/* dbs_bin_sort for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same tile lists, bit for bit, with the scratch taken from a fixed
+ * device array of DBS_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * GPU it runs on until the process ends, instead of a caller workspace.
+ * Allocates nothing (no hipMalloc, no allocating library call).  Returns
+ * DBS_ERR_CAPACITY when the scratch the call needs, dbs_workspace_bytes(n,
+ * n_views, pair_capacity, cams, cfg), exceeds DBS_NOALLOC_SCRATCH_BYTES.
+ * All calls on one GPU share that GPU's array, which keeps the last call's
+ * contents (nothing in it needs to start at zero): calls that overlap on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller.  Other arguments, results and errors as dbs_bin_sort. */
+#define DBS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dbs_status dbs_bin_sort_noalloc(const void *projected, const dbs_camera *cams /*[host]*/, int32_t n_views,
+                                const dbs_raster_cfg *cfg /*[host]*/, int64_t n, int64_t pair_capacity,
+                                void *bins, size_t bins_bytes, int32_t *overflow /* device int32 or NULL */,
+                                void *stream);
+
 /* Front-to-back compositing, Sec. 3.2 Eq. (6), of every pixel of every view:
  *   image      [3 * sum(W H)] FP32, planar per view (see above);
  *               colour = sum_i c_i alpha_i T_i + T_final * background

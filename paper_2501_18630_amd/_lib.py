@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libdbs.so")
 OK, ERR_INVALID_ARGUMENT, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED = range(5)
 MAX_LOBES = 8
 MAX_VIEWS = 1024
+NOALLOC_SCRATCH_BYTES = 64 << 20
 FLAG_PERSISTENT = 1
 FLAG_DIFFUSE_ONLY = 2
 FLAG_SPECULAR_ONLY = 4
@@ -27,7 +28,7 @@ PARAMS = ("means", "scales", "quats", "opacities", "betas", "diffuse",
           "lobe_angles", "lobe_colors", "lobe_betas")
 
 EXPORTS = ("dbs_default_cfg", "dbs_projected_bytes", "dbs_bins_bytes", "dbs_workspace_bytes",
-           "dbs_preprocess", "dbs_preprocess_gaussian_sh", "dbs_bin_sort", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
+           "dbs_preprocess", "dbs_preprocess_gaussian_sh", "dbs_bin_sort", "dbs_bin_sort_noalloc", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
            "dbs_photometric_loss", "dbs_regularizer", "dbs_mcmc_workspace_bytes", "dbs_mcmc_relocate",
            "dbs_mcmc_noise",
            "dbs_raster_bwd", "dbs_raster_bwd_count", "dbs_project_bwd", "dbs_render_stats",
@@ -75,6 +76,7 @@ def _declare(lib):
     lib.dbs_preprocess.argtypes = [P, P, I32, P, P, SZ, P, P]
     lib.dbs_preprocess_gaussian_sh.argtypes = [P, P, P, I32, P, P, SZ, P, P]
     lib.dbs_bin_sort.argtypes = [P, P, I32, P, I64, I64, P, SZ, P, SZ, P, P]
+    lib.dbs_bin_sort_noalloc.argtypes = [P, P, I32, P, I64, I64, P, SZ, P, P]
     lib.dbs_render_fwd.argtypes = [P, P, P, I32, P, I64, P, P, P, P]
     lib.dbs_render_bwd.argtypes = [P, P, P, P, I32, P, P, P, P, P, P]
     lib.dbs_raster_bwd.argtypes = [P, P, P, I32, P, I64, P, P, P, P]
@@ -90,7 +92,7 @@ def _declare(lib):
     lib.dbs_mcmc_noise.argtypes = [P, P, C.c_float, C.c_float, C.c_float, P]
     lib.dbs_projected_layout.argtypes = [P, I64, I32] + [C.POINTER(C.c_void_p)] * 5
     lib.dbs_bins_layout.argtypes = [P, I64, P, I32, P] + [C.POINTER(C.c_void_p)] * 3 + [C.POINTER(C.c_int64)]
-    for f in ("dbs_preprocess", "dbs_preprocess_gaussian_sh", "dbs_bin_sort", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
+    for f in ("dbs_preprocess", "dbs_preprocess_gaussian_sh", "dbs_bin_sort", "dbs_bin_sort_noalloc", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
               "dbs_photometric_loss", "dbs_regularizer", "dbs_mcmc_workspace_bytes", "dbs_mcmc_relocate",
            "dbs_mcmc_noise", "dbs_raster_bwd", "dbs_raster_bwd_count", "dbs_project_bwd", "dbs_render_stats",
               "dbs_projected_layout", "dbs_bins_layout"):

@@ -192,6 +192,29 @@ dbs_status dbs_bin_sort(const void *projected, const dbs_camera *cams, int32_t n
                                       cfg->tile_h, overflow, (hipStream_t)stream));
 }
 
+dbs_status dbs_bin_sort_noalloc(const void *projected, const dbs_camera *cams, int32_t n_views,
+                                const dbs_raster_cfg *cfg, int64_t n, int64_t pair_capacity, void *bins,
+                                size_t bins_bytes, int32_t *overflow, void *stream)
+{
+    DBS_TRY(check_cams(cams, n_views));
+    DBS_TRY(check_cfg(cfg));
+    DBS_TRY(check_sizes(n, n_views));
+    if (!projected || !bins) return DBS_ERR_INVALID_ARGUMENT;
+    if (pair_capacity < 0) return DBS_ERR_INVALID_ARGUMENT;
+    if (pair_capacity > DBS_MAX_PAIRS) return DBS_ERR_UNSUPPORTED;
+    const int64_t n_tiles = total_tiles(cams, n_views, cfg->tile_w, cfg->tile_h);
+    if (n_tiles >= 0xffffffffll) return DBS_ERR_UNSUPPORTED;
+    if (bins_bytes < bins_layout(pair_capacity, n_tiles).total) return DBS_ERR_CAPACITY;
+    if (work_layout(n, n_views, pair_capacity, n_tiles).total > (size_t)DBS_NOALLOC_SCRATCH_BYTES)
+        return DBS_ERR_CAPACITY;
+    void *work = nullptr;
+    DBS_TRY(hip_status(noalloc_scratch(&work)));
+    ProjPtrs P = proj_ptrs((void *)projected, n, n_views);
+    BinsPtrs B = bins_ptrs(bins, n_tiles);
+    return hip_status(launch_bin_sort(P, B, work, n, n_views, pair_capacity, n_tiles, cfg->tile_w, cfg->tile_h,
+                                      overflow, (hipStream_t)stream));
+}
+
 dbs_status dbs_render_fwd(const void *projected, const void *bins, const dbs_camera *cams, int32_t n_views,
                           const dbs_raster_cfg *cfg, int64_t n, float *image, float *final_T, int32_t *last_index,
                           void *stream)

@@ -237,6 +237,9 @@ hipError_t launch_upload_views(const dbs_camera *cams, int32_t n_views, int tile
 hipError_t launch_preprocess(const SplatPtrs &sp, const float *sh, ProjPtrs P, int32_t n_views, int tile_w,
                              int tile_h, uint32_t flags, float b_split, int64_t *counts, hipStream_t s);
 // sort.hip
+// the device address of dbs_bin_sort_noalloc's scratch on the current device
+// (DBS_NOALLOC_SCRATCH_BYTES), looked up once per device
+hipError_t noalloc_scratch(void **out);
 hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_t n_views,
                            int64_t cap, int64_t n_tiles, int tile_w, int tile_h,
                            int32_t *overflow_out, hipStream_t s);

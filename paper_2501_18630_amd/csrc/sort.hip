@@ -20,6 +20,8 @@
 // barrier per phase) and writes them out digit-contiguous.  Element counts
 // are read from device memory, so the whole pipeline runs without a host
 // round trip and can be captured in a graph.
+#include <mutex>
+
 #include "dbs_internal.h"
 
 namespace dbs {
@@ -643,6 +645,35 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- allocation-free entry point
+
+// Scratch of dbs_bin_sort_noalloc: one fixed array per GPU, held from the
+// library's load until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it only names the symbol); it passes the
+// device address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[DBS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+hipError_t noalloc_scratch(void **out)
+{
+    static std::mutex mu;
+    static void *per_device[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!per_device[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        per_device[dev] = ptr;
+    }
+    *out = per_device[dev];
+    return hipSuccess;
 }
 
 }  // namespace dbs
