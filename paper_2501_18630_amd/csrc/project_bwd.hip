@@ -20,11 +20,12 @@
 // Colour (Sec. 3.3, Eq. 8): c = c0 + sum_m max(R_m.V, 0)^{beta_m} c_m,
 //   beta_m = 4 e^{b_m}, V = (mu - campos)/|mu - campos|.
 //
-// One thread per splat loops over the views: the per-splat gradient is summed
-// in registers (no atomics), Sigma's adjoint is summed over views before the
-// single chain to (q, s), and parameters are read and gradients written once.
-// Two kernels with disjoint register needs: the geometric chain (FP64) and
-// the colour chain (Spherical Beta lobes in FP32), which clears the lines.
+// Each splat's per-view terms are summed over the views before the single
+// chain to (q, s), and parameters are read and gradients written once.  The
+// per-view terms are computed on packed work lists of the visible records
+// (see below), each added into its splat's accumulators in LDS.  Two kernels
+// with disjoint register needs: the geometric chain (FP64) and the colour
+// chain (Spherical Beta lobes in FP32), which clears the lines.
 #include "dbs_internal.h"
 
 namespace dbs {
@@ -44,132 +45,187 @@ __device__ __forceinline__ bool line_is_zero(const float4 a, const float4 b, con
            b.w == 0.f && c.x == 0.f && c.y == 0.f;
 }
 
+// Work lists.  A splat is seen by only some of the views, and a thread that
+// loops over every view for its own splat idles in the views it does not
+// see (a quarter of the lanes were busy).  Instead, each wavefront lists the
+// (splat, view) records of its 64 splats that the views see -- view-major,
+// a window of kItemViews views at a time -- and processes that list 64
+// records at a time, every lane busy.  A record's terms are added into its
+// splat's accumulators in LDS; a splat appears at most once per view, and
+// the list is view-major, so a splat's terms are added in view order.
+// The per-splat parts (Sigma from q and s before, the chain to q and s after)
+// are done by the splat's own lane.
+constexpr int kPackWaves = 4;
+constexpr int kItemViews = 16;  // divides 64: a window's visibility bits share one word
+static_assert(64 % kItemViews == 0, "item windows must not straddle visibility words");
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
+
+// Lists the records (lane, v), v in [v0, v1), of the wavefront's splats that
+// view v sees, view-major; returns the count.  item = lane | v << 6.
+__device__ __forceinline__ int list_items(uint64_t vm, bool live, int v0, int v1, uint16_t *items, int lane)
+{
+    int cnt = 0;
+    for (int v = v0; v < v1; ++v) {
+        const bool vis = live && ((vm >> (v & 63)) & 1u);
+        const uint64_t b = __ballot(vis);
+        if (vis) items[cnt + __popcll(b & lanes_below(lane))] = (uint16_t)(lane | (v << 6));
+        cnt += __popcll(b);
+    }
+    return cnt;
+}
+
 // Geometry: dL/dmu' (2), dL/dA (3), dL/do, dL/db  ->  mu, s, q, o, b.  FP64.
 // store: write the gradients instead of adding them (every splat is written,
 // zeros for a splat that no view sees).
-__global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
-                                                                   GradPtrs g, int store)
+__global__ __launch_bounds__(64 * kPackWaves) void project_bwd_geometry_kernel(SplatPtrs sp, ProjPtrs P,
+                                                                               int32_t n_views, GradPtrs g, int store)
 {
+    constexpr int NA = 11;  // accumulators: dL/dmu (3), dL/do, dL/db, adjoint of Sigma (xx xy xz yy yz zz)
+    __shared__ double s_sig[kPackWaves][6][kWave];
+    __shared__ double s_acc[kPackWaves][NA][kWave];
+    __shared__ float s_mu[kPackWaves][3][kWave];
+    __shared__ int s_any[kPackWaves][kWave];
+    __shared__ uint16_t s_item[kPackWaves][kWave * kItemViews];
     const int64_t n = sp.n;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !proj_matches(P, n, n_views)) return;
+    if (!proj_matches(P, n, n_views)) return;  // the same for the whole grid
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (int64_t)w * kWave;  // the wavefront's first splat
+    const int64_t i = i0 + lane;
+    const bool live = i < n;
 
-    const double mu[3] = {sp.means[3 * i], sp.means[3 * i + 1], sp.means[3 * i + 2]};
-    double qv[4] = {sp.quats[4 * i], sp.quats[4 * i + 1], sp.quats[4 * i + 2], sp.quats[4 * i + 3]};
-    const double qn = sqrt(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3]);
-    const double iqn = 1.0 / qn;
-    for (int k = 0; k < 4; ++k) qv[k] *= iqn;
-    const double sc[3] = {sp.scales[3 * i], sp.scales[3 * i + 1], sp.scales[3 * i + 2]};
-    double Sig[6];  // xx xy xz yy yz zz
-    {
-        const double w = qv[0], x = qv[1], y = qv[2], z = qv[3];
-        const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
-                             2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
-                             2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+    double qv[4] = {1.0, 0.0, 0.0, 0.0}, sc[3] = {0.0, 0.0, 0.0}, iqn = 1.0;
+    if (live) {
+        for (int k = 0; k < 4; ++k) qv[k] = sp.quats[4 * i + k];
+        const double qn = sqrt(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3]);
+        iqn = 1.0 / qn;
+        for (int k = 0; k < 4; ++k) qv[k] *= iqn;
+        for (int k = 0; k < 3; ++k) {
+            sc[k] = sp.scales[3 * i + k];
+            s_mu[w][k][lane] = sp.means[3 * i + k];
+        }
+        const double w_ = qv[0], x = qv[1], y = qv[2], z = qv[3];
+        const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w_ * z), 2.0 * (x * z + w_ * y),
+                             2.0 * (x * y + w_ * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w_ * x),
+                             2.0 * (x * z - w_ * y), 2.0 * (y * z + w_ * x), 1.0 - 2.0 * (x * x + y * y)};
         const double s2[3] = {sc[0] * sc[0], sc[1] * sc[1], sc[2] * sc[2]};
         int e = 0;
         for (int a = 0; a < 3; ++a)
             for (int b = a; b < 3; ++b)
-                Sig[e++] = R[3 * a] * s2[0] * R[3 * b] + R[3 * a + 1] * s2[1] * R[3 * b + 1] +
-                           R[3 * a + 2] * s2[2] * R[3 * b + 2];
+                s_sig[w][e++][lane] = R[3 * a] * s2[0] * R[3 * b] + R[3 * a + 1] * s2[1] * R[3 * b + 1] +
+                                      R[3 * a + 2] * s2[2] * R[3 * b + 2];
     }
+    for (int c = 0; c < NA; ++c) s_acc[w][c][lane] = 0.0;
+    s_any[w][lane] = 0;
 
-    double gmu[3] = {0, 0, 0}, go = 0, gb = 0;
-    double dS[6] = {0, 0, 0, 0, 0, 0};  // adjoint of Sigma (full-matrix entries xx xy xz yy yz zz)
-    bool any = false;
-
-    // Lines of records the raster pass never touched (culled, or no pixel
-    // reached) are zero; those of culled records are not even read (the
-    // preprocess's visibility bits).  Each view's line is loaded one view ahead
-    // so that its latency overlaps the previous view's arithmetic.
-    uint64_t vm = P.vismask[i];
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 na = z4, nb = z4;
-    if (vm & 1u) {
-        na = P.sgrad[4 * i];
-        nb = P.sgrad[4 * i + 1];
-    }
-    for (int32_t v = 0; v < n_views; ++v) {
-        const float4 ga = na, gbv = nb;
-        const bool vis = (vm >> (v & 63)) & 1u;
-        na = nb = z4;
-        if (v + 1 < n_views) {
-            if (((v + 1) & 63) == 0) vm = P.vismask[(int64_t)((v + 1) >> 6) * n + i];
-            if ((vm >> ((v + 1) & 63)) & 1u) {
-                const float4 *nl = P.sgrad + 4 * ((int64_t)(v + 1) * n + i);
-                na = nl[0];
-                nb = nl[1];
+    for (int v0 = 0; v0 < n_views; v0 += kItemViews) {
+        const int v1 = v0 + kItemViews < n_views ? v0 + kItemViews : n_views;
+        const uint64_t vm = live ? P.vismask[(int64_t)(v0 >> 6) * n + i] : 0ull;
+        const int cnt = list_items(vm, live, v0, v1, s_item[w], lane);
+        __syncthreads();
+        // each group's accumulator lines are loaded while the previous group computes
+        // ga = (dmu'x, dmu'y, G00, G01), gbv = (G11, do, db, -); lines the raster pass never touched are zero
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        bool has_n = lane < cnt;
+        int item_n = has_n ? s_item[w][lane] : 0;
+        float4 ga_n = z4, gbv_n = z4;
+        if (has_n) {
+            const float4 *line = P.sgrad + 4 * ((int64_t)(item_n >> 6) * n + i0 + (item_n & (kWave - 1)));
+            ga_n = line[0];
+            gbv_n = line[1];
+        }
+        for (int base = 0; base < cnt; base += kWave) {
+            const bool has = has_n;
+            const int item = item_n;
+            const float4 ga = ga_n, gbv = gbv_n;
+            const int kn = base + kWave + lane;
+            has_n = kn < cnt;
+            item_n = has_n ? s_item[w][kn] : 0;
+            ga_n = gbv_n = z4;
+            if (has_n) {
+                const float4 *line = P.sgrad + 4 * ((int64_t)(item_n >> 6) * n + i0 + (item_n & (kWave - 1)));
+                ga_n = line[0];
+                gbv_n = line[1];
             }
-        }
-        if (!vis) continue;
-        // ga = (dmu'x, dmu'y, G00, G01), gbv = (G11, do, db, -)
-        if (ga.x == 0.f && ga.y == 0.f && ga.z == 0.f && ga.w == 0.f && gbv.x == 0.f && gbv.y == 0.f &&
-            gbv.z == 0.f)
-            continue;
-        any = true;
-        go += gbv.y;
-        gb += gbv.z;
-        ConstViewDesc &V = const_view(P.views, v);
-        const double W[9] = {V.R[0], V.R[1], V.R[2], V.R[3], V.R[4], V.R[5], V.R[6], V.R[7], V.R[8]};
-        const double tx = W[0] * mu[0] + W[1] * mu[1] + W[2] * mu[2] + (double)V.t[0];
-        const double ty = W[3] * mu[0] + W[4] * mu[1] + W[5] * mu[2] + (double)V.t[1];
-        const double tz = W[6] * mu[0] + W[7] * mu[1] + W[8] * mu[2] + (double)V.t[2];
-        const double fx = V.fx, fy = V.fy;
-        const double iz = 1.0 / tz, iz2 = iz * iz;
-        const double J00 = fx * iz, J02 = -fx * tx * iz2, J11 = fy * iz, J12 = -fy * ty * iz2;
-        double Mm[2][3];
-        for (int b = 0; b < 3; ++b) {
-            Mm[0][b] = J00 * W[b] + J02 * W[6 + b];
-            Mm[1][b] = J11 * W[3 + b] + J12 * W[6 + b];
-        }
-        double Tm[2][3];  // M Sigma
-        for (int a = 0; a < 2; ++a) {
-            Tm[a][0] = Mm[a][0] * Sig[0] + Mm[a][1] * Sig[1] + Mm[a][2] * Sig[2];
-            Tm[a][1] = Mm[a][0] * Sig[1] + Mm[a][1] * Sig[3] + Mm[a][2] * Sig[4];
-            Tm[a][2] = Mm[a][0] * Sig[2] + Mm[a][1] * Sig[4] + Mm[a][2] * Sig[5];
-        }
-        const double c00 = Tm[0][0] * Mm[0][0] + Tm[0][1] * Mm[0][1] + Tm[0][2] * Mm[0][2];
-        const double c01 = Tm[0][0] * Mm[1][0] + Tm[0][1] * Mm[1][1] + Tm[0][2] * Mm[1][2];
-        const double c11 = Tm[1][0] * Mm[1][0] + Tm[1][1] * Mm[1][1] + Tm[1][2] * Mm[1][2];
-        const double idet = 1.0 / (c00 * c11 - c01 * c01);
-        const double A00 = c11 * idet, A01 = -c01 * idet, A11 = c00 * idet;
-
-        // conic -> Sigma':  dC = -A G A
-        const double G00 = ga.z, G01 = ga.w, G11 = gbv.x;
-        const double AG00 = A00 * G00 + A01 * G01, AG01 = A00 * G01 + A01 * G11;
-        const double AG10 = A01 * G00 + A11 * G01, AG11 = A01 * G01 + A11 * G11;
-        const double dC00 = -(AG00 * A00 + AG01 * A01);
-        const double dC01 = -(AG00 * A01 + AG01 * A11);
-        const double dC11 = -(AG10 * A01 + AG11 * A11);
-        // dSigma += M^T dC M (symmetric)
-        {
-            double P0[3], P1[3];  // rows of dC M
+            if (!has) continue;
+            if (ga.x == 0.f && ga.y == 0.f && ga.z == 0.f && ga.w == 0.f && gbv.x == 0.f && gbv.y == 0.f &&
+                gbv.z == 0.f)
+                continue;
+            const int j = item & (kWave - 1), v = item >> 6;
+            s_any[w][j] = 1;
+            const ViewDesc &V = P.views[v];
+            const double mu[3] = {s_mu[w][0][j], s_mu[w][1][j], s_mu[w][2][j]};
+            double Sig[6];
+            for (int e = 0; e < 6; ++e) Sig[e] = s_sig[w][e][j];
+            const double W[9] = {V.R[0], V.R[1], V.R[2], V.R[3], V.R[4], V.R[5], V.R[6], V.R[7], V.R[8]};
+            const double tx = W[0] * mu[0] + W[1] * mu[1] + W[2] * mu[2] + (double)V.t[0];
+            const double ty = W[3] * mu[0] + W[4] * mu[1] + W[5] * mu[2] + (double)V.t[1];
+            const double tz = W[6] * mu[0] + W[7] * mu[1] + W[8] * mu[2] + (double)V.t[2];
+            const double fx = V.fx, fy = V.fy;
+            const double iz = 1.0 / tz, iz2 = iz * iz;
+            const double J00 = fx * iz, J02 = -fx * tx * iz2, J11 = fy * iz, J12 = -fy * ty * iz2;
+            double Mm[2][3];
             for (int b = 0; b < 3; ++b) {
-                P0[b] = dC00 * Mm[0][b] + dC01 * Mm[1][b];
-                P1[b] = dC01 * Mm[0][b] + dC11 * Mm[1][b];
+                Mm[0][b] = J00 * W[b] + J02 * W[6 + b];
+                Mm[1][b] = J11 * W[3 + b] + J12 * W[6 + b];
             }
-            int e = 0;
-            for (int a = 0; a < 3; ++a)
-                for (int b = a; b < 3; ++b) dS[e++] += Mm[0][a] * P0[b] + Mm[1][a] * P1[b];
+            double Tm[2][3];  // M Sigma
+            for (int a = 0; a < 2; ++a) {
+                Tm[a][0] = Mm[a][0] * Sig[0] + Mm[a][1] * Sig[1] + Mm[a][2] * Sig[2];
+                Tm[a][1] = Mm[a][0] * Sig[1] + Mm[a][1] * Sig[3] + Mm[a][2] * Sig[4];
+                Tm[a][2] = Mm[a][0] * Sig[2] + Mm[a][1] * Sig[4] + Mm[a][2] * Sig[5];
+            }
+            const double c00 = Tm[0][0] * Mm[0][0] + Tm[0][1] * Mm[0][1] + Tm[0][2] * Mm[0][2];
+            const double c01 = Tm[0][0] * Mm[1][0] + Tm[0][1] * Mm[1][1] + Tm[0][2] * Mm[1][2];
+            const double c11 = Tm[1][0] * Mm[1][0] + Tm[1][1] * Mm[1][1] + Tm[1][2] * Mm[1][2];
+            const double idet = 1.0 / (c00 * c11 - c01 * c01);
+            const double A00 = c11 * idet, A01 = -c01 * idet, A11 = c00 * idet;
+
+            // conic -> Sigma':  dC = -A G A
+            const double G00 = ga.z, G01 = ga.w, G11 = gbv.x;
+            const double AG00 = A00 * G00 + A01 * G01, AG01 = A00 * G01 + A01 * G11;
+            const double AG10 = A01 * G00 + A11 * G01, AG11 = A01 * G01 + A11 * G11;
+            const double dC00 = -(AG00 * A00 + AG01 * A01);
+            const double dC01 = -(AG00 * A01 + AG01 * A11);
+            const double dC11 = -(AG10 * A01 + AG11 * A11);
+            // dSigma += M^T dC M (symmetric)
+            double dS[6];
+            {
+                double P0[3], P1[3];  // rows of dC M
+                for (int b = 0; b < 3; ++b) {
+                    P0[b] = dC00 * Mm[0][b] + dC01 * Mm[1][b];
+                    P1[b] = dC01 * Mm[0][b] + dC11 * Mm[1][b];
+                }
+                int e = 0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = a; b < 3; ++b) dS[e++] = Mm[0][a] * P0[b] + Mm[1][a] * P1[b];
+            }
+            // dM = 2 dC M Sigma = 2 dC Tm ; dJ = dM W^T (the non-zero entries of J)
+            double dM0[3], dM1[3];
+            for (int b = 0; b < 3; ++b) {
+                dM0[b] = 2.0 * (dC00 * Tm[0][b] + dC01 * Tm[1][b]);
+                dM1[b] = 2.0 * (dC01 * Tm[0][b] + dC11 * Tm[1][b]);
+            }
+            const double dJ00 = dM0[0] * W[0] + dM0[1] * W[1] + dM0[2] * W[2];
+            const double dJ02 = dM0[0] * W[6] + dM0[1] * W[7] + dM0[2] * W[8];
+            const double dJ11 = dM1[0] * W[3] + dM1[1] * W[4] + dM1[2] * W[5];
+            const double dJ12 = dM1[0] * W[6] + dM1[1] * W[7] + dM1[2] * W[8];
+            const double iz3 = iz2 * iz;
+            const double dt0 = dJ02 * (-fx * iz2) + ga.x * fx * iz;
+            const double dt1 = dJ12 * (-fy * iz2) + ga.y * fy * iz;
+            const double dt2 = dJ00 * (-fx * iz2) + dJ02 * (2.0 * fx * tx * iz3) + dJ11 * (-fy * iz2) +
+                               dJ12 * (2.0 * fy * ty * iz3) - ga.x * fx * tx * iz2 - ga.y * fy * ty * iz2;
+            // this record's terms into the splat's accumulators
+            for (int k3 = 0; k3 < 3; ++k3)
+                atomicAdd(&s_acc[w][k3][j], W[k3] * dt0 + W[3 + k3] * dt1 + W[6 + k3] * dt2);
+            atomicAdd(&s_acc[w][3][j], (double)gbv.y);
+            atomicAdd(&s_acc[w][4][j], (double)gbv.z);
+            for (int e = 0; e < 6; ++e) atomicAdd(&s_acc[w][5 + e][j], dS[e]);
         }
-        // dM = 2 dC M Sigma = 2 dC Tm ; dJ = dM W^T (the non-zero entries of J)
-        double dM0[3], dM1[3];
-        for (int b = 0; b < 3; ++b) {
-            dM0[b] = 2.0 * (dC00 * Tm[0][b] + dC01 * Tm[1][b]);
-            dM1[b] = 2.0 * (dC01 * Tm[0][b] + dC11 * Tm[1][b]);
-        }
-        const double dJ00 = dM0[0] * W[0] + dM0[1] * W[1] + dM0[2] * W[2];
-        const double dJ02 = dM0[0] * W[6] + dM0[1] * W[7] + dM0[2] * W[8];
-        const double dJ11 = dM1[0] * W[3] + dM1[1] * W[4] + dM1[2] * W[5];
-        const double dJ12 = dM1[0] * W[6] + dM1[1] * W[7] + dM1[2] * W[8];
-        const double iz3 = iz2 * iz;
-        const double dt0 = dJ02 * (-fx * iz2) + ga.x * fx * iz;
-        const double dt1 = dJ12 * (-fy * iz2) + ga.y * fy * iz;
-        const double dt2 = dJ00 * (-fx * iz2) + dJ02 * (2.0 * fx * tx * iz3) + dJ11 * (-fy * iz2) +
-                           dJ12 * (2.0 * fy * ty * iz3) - ga.x * fx * tx * iz2 - ga.y * fy * ty * iz2;
-        for (int k = 0; k < 3; ++k) gmu[k] += W[k] * dt0 + W[3 + k] * dt1 + W[6 + k] * dt2;
+        __syncthreads();  // the list is rebuilt for the next window
     }
-    if (!any) {
+    if (!live) return;
+    if (!s_any[w][lane]) {
         if (store) {
             for (int k = 0; k < 3; ++k) {
                 g.means[3 * i + k] = 0.0f;
@@ -181,12 +237,16 @@ __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp,
         }
         return;
     }
+    const double gmu[3] = {s_acc[w][0][lane], s_acc[w][1][lane], s_acc[w][2][lane]};
+    const double go = s_acc[w][3][lane], gb = s_acc[w][4][lane];
+    double dS[6];
+    for (int e = 0; e < 6; ++e) dS[e] = s_acc[w][5 + e][lane];
 
     // Sigma = R diag(s^2) R^T  ->  s and the normalised quaternion
-    const double w = qv[0], x = qv[1], y = qv[2], z = qv[3];
-    const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
-                         2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
-                         2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+    const double w_ = qv[0], x = qv[1], y = qv[2], z = qv[3];
+    const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w_ * z), 2.0 * (x * z + w_ * y),
+                         2.0 * (x * y + w_ * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w_ * x),
+                         2.0 * (x * z - w_ * y), 2.0 * (y * z + w_ * x), 1.0 - 2.0 * (x * x + y * y)};
     const double D[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
     double dR[9], gs[3];
     for (int r = 0; r < 3; ++r)
@@ -203,10 +263,10 @@ __global__ __launch_bounds__(256) void project_bwd_geometry_kernel(SplatPtrs sp,
     }
     double dq[4];
     dq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-    dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] - 2.0 * x * dR[8]);
-    dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] - 2.0 * y * dR[8]);
-    dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] + y * dR[7]);
-    const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+    dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w_ * dR[5] + z * dR[6] + w_ * dR[7] - 2.0 * x * dR[8]);
+    dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w_ * dR[2] + x * dR[3] + z * dR[5] - w_ * dR[6] + z * dR[7] - 2.0 * y * dR[8]);
+    dq[3] = 2.0 * (-2.0 * z * dR[0] - w_ * dR[1] + x * dR[2] + w_ * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] + y * dR[7]);
+    const double qd = w_ * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
     float out[12];
     for (int k = 0; k < 3; ++k) {
         out[k] = (float)gmu[k];
@@ -432,11 +492,13 @@ hipError_t launch_project_bwd(const SplatPtrs &sp, ProjPtrs P, int32_t n_views, 
                               hipStream_t s)
 {
     if (sp.n <= 0) return hipSuccess;
-    dim3 grid((unsigned)ceil_div(sp.n, 256));
     const int st = store ? 1 : 0;
-    project_bwd_geometry_kernel<<<grid, 256, 0, s>>>(sp, P, n_views, g, st);
+    project_bwd_geometry_kernel<<<(unsigned)ceil_div(sp.n, 64 * kPackWaves), 64 * kPackWaves, 0, s>>>(sp, P, n_views,
+                                                                                                    g, st);
     switch (sp.m) {
-#define DBS_PB(MM) case MM: project_bwd_color_kernel<MM><<<grid, 256, 0, s>>>(sp, P, n_views, g, st); break;
+#define DBS_PB(MM)                                                                                          \
+    case MM: project_bwd_color_kernel<MM><<<(unsigned)ceil_div(sp.n, 256), 256, 0, s>>>(sp, P, n_views, g, st); \
+        break;
         DBS_PB(0) DBS_PB(1) DBS_PB(2) DBS_PB(3) DBS_PB(4) DBS_PB(5) DBS_PB(6) DBS_PB(7) DBS_PB(8)
 #undef DBS_PB
         default: return hipErrorInvalidValue;
