@@ -123,7 +123,7 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct WorkLayout {
     // bin/sort phase
-    size_t keys_a, vals_a, keys_b, vals_b, pair_off, pkeys_a, pkeys_b, pvals_b, hist, partials,
+    size_t keys_a, vals_a, keys_b, vals_b, block_sum, group_sum, pkeys_a, pkeys_b, pvals_b, hist, partials,
         tkeys_a, tvals_a, tkeys_b, sorted_box, sort_total;
     size_t total;
     int64_t hist_blocks;  // max sort blocks of any sort
@@ -141,7 +141,10 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     L.vals_a = o;   o = align_up(o + 4 * R);
     L.keys_b = o;   o = align_up(o + 4 * R);
     L.vals_b = o;   o = align_up(o + 4 * R);
-    L.pair_off = o; o = align_up(o + 4 * (R + 1));
+    // output offsets of blocks of 4096 records (compaction, pair counts) and
+    // the pair counts of their groups of 256 records (pair emission)
+    L.block_sum = o; o = align_up(o + 4 * (size_t)ceil_div((int64_t)R > 0 ? (int64_t)R : 1, 4096));
+    L.group_sum = o; o = align_up(o + 4 * (size_t)ceil_div((int64_t)R > 0 ? (int64_t)R : 1, 256));
     L.pkeys_a = o;  o = align_up(o + 4 * (size_t)cap);
     L.pkeys_b = o;  o = align_up(o + 4 * (size_t)cap);
     L.pvals_b = o;  o = align_up(o + 4 * (size_t)cap);

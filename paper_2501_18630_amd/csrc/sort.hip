@@ -97,9 +97,16 @@ __global__ __launch_bounds__(kSortThreads) void scan_reduce_kernel(Load ld, Coun
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
-// Single-block exclusive scan of partials[0..nb), in place.
-__global__ __launch_bounds__(1024) void scan_partials_kernel(uint32_t *partials, int64_t nb)
+// Single-block exclusive scan of partials[0..nb), in place.  With `items`
+// set, only the ceil(*items / per_block) partials of blocks that hold items
+// are scanned (the grid before it was sized for the capacity).
+__global__ __launch_bounds__(1024) void scan_partials_kernel(uint32_t *partials, int64_t nb,
+                                                             const uint32_t *items = nullptr, int per_block = 1)
 {
+    if (items) {
+        const int64_t used = ((int64_t)*items + per_block - 1) / per_block;
+        if (used < nb) nb = used;
+    }
     __shared__ uint32_t s_w[1024 / kWave + 1];
     __shared__ uint32_t s_carry;
     if (threadIdx.x == 0) s_carry = 0;
@@ -441,79 +448,243 @@ __global__ void finalize_counts_kernel(const ProjHeader *ph, BinsHeader *bh, int
     if (overflow_out) *overflow_out = ovf;
 }
 
-struct LoadVisible {
-    const uint32_t *ntiles;
-    __device__ uint32_t operator()(int64_t i) const { return ntiles[i] > 0 ? 1u : 0u; }
-};
-struct LoadTilesOfBox {
-    const uint2 *box;  // sorted pixel boxes (int16 x_lo, x_hi, y_lo, y_hi)
-    int tw, th;
-    __device__ uint32_t operator()(int64_t j) const
-    {
-        const uint2 u = box[j];
-        const int xl = (int)(int16_t)(u.x & 0xffffu), xh = (int)(int16_t)(u.x >> 16);
-        const int yl = (int)(int16_t)(u.y & 0xffffu), yh = (int)(int16_t)(u.y >> 16);
-        return (uint32_t)((xh / tw - xl / tw + 1) * (yh / th - yl / th + 1));
-    }
-};
-struct StoreCompact {
-    const uint32_t *depth;
-    uint32_t *keys, *vals;
-    __device__ void operator()(int64_t i, uint32_t pre, uint32_t v) const
-    {
-        if (v) {
-            keys[pre] = depth[i];
-            vals[pre] = (uint32_t)i;
-        }
-    }
-};
+// Compaction of the visible records (tile count > 0) in record order: each
+// block takes 4096 consecutive records (16 consecutive ones per thread, read
+// as four 16-byte loads); a first pass counts each block's visible records,
+// their exclusive scan gives each block its output offset, and a second pass
+// ranks the visible records inside the block and writes the (depth key,
+// record) pairs contiguously through LDS.
+constexpr int kCompactItems = 16;
+constexpr int kCompactTile = kSortThreads * kCompactItems;
 
-// One block per 256 depth-ordered records: the block's pairs are generated
-// cooperatively, thread p writing pair p of the block (found by binary search
-// over the records' pair offsets), so that every store is contiguous.  (An
-// XCD-ordered chunk assignment, as in the radix passes, measured slower here.)
-__global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, const uint32_t *sorted_rec,
-                                                         const uint32_t *pair_off, const short4 *sorted_box,
-                                                         const ViewDesc *views, uint32_t n, int tw, int th,
-                                                         uint32_t *pkeys, uint32_t *pvals)
+__device__ __forceinline__ void load_counts16(const uint32_t *ntiles, int64_t e0, int64_t n, uint32_t nt[16])
 {
-    // pairs are only emitted below n_pairs (at most the capacity)
+    if (e0 + kCompactItems <= n) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(ntiles + e0);
+#pragma unroll
+        for (int q = 0; q < kCompactItems / 4; ++q) {
+            const uint4 u = src[q];
+            nt[4 * q] = u.x;
+            nt[4 * q + 1] = u.y;
+            nt[4 * q + 2] = u.z;
+            nt[4 * q + 3] = u.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kCompactItems; ++q) nt[q] = e0 + q < n ? ntiles[e0 + q] : 0u;
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void count_visible_kernel(const BinsHeader *bh, const uint32_t *ntiles,
+                                                                     uint32_t *partials)
+{
+    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
+    const int64_t n = bh->n_rec;  // 0 when the buffers do not match
+    const int64_t e0 = (int64_t)blockIdx.x * kCompactTile + (int64_t)threadIdx.x * kCompactItems;
+    uint32_t nt[kCompactItems];
+    load_counts16(ntiles, e0, n, nt);
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kCompactItems; ++q) cnt += nt[q] > 0u;
+    uint32_t total;
+    block_exclusive_scan(cnt, s_tmp, &total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kSortThreads) void compact_visible_kernel(const BinsHeader *bh, const uint32_t *ntiles,
+                                                                       const uint32_t *depth,
+                                                                       const uint32_t *offsets, uint32_t *keys,
+                                                                       uint32_t *vals)
+{
+    __shared__ uint2 s_out[kCompactTile];
+    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
+    const int64_t n = bh->n_rec;
+    const int64_t base = (int64_t)blockIdx.x * kCompactTile;
+    if (base >= n) return;  // uniform
+    const int t = threadIdx.x;
+    const int64_t e0 = base + (int64_t)t * kCompactItems;
+    uint32_t nt[kCompactItems];
+    load_counts16(ntiles, e0, n, nt);
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < kCompactItems; ++q) cnt += nt[q] > 0u;
+    uint32_t total;
+    uint32_t r = block_exclusive_scan(cnt, s_tmp, &total);
+#pragma unroll
+    for (int q = 0; q < kCompactItems; ++q)
+        if (nt[q] > 0u) s_out[r++] = make_uint2(depth[e0 + q], (uint32_t)(e0 + q));
+    __syncthreads();
+    const uint32_t out = offsets[blockIdx.x];
+    for (uint32_t j = t; j < total; j += kSortThreads) {
+        const uint2 kv = s_out[j];
+        keys[out + j] = kv.x;
+        vals[out + j] = kv.y;
+    }
+}
+
+// Tile rectangle of a sorted record's pixel box (tile sides 2^lw x 2^lh;
+// boxes are clipped to the image, so the coordinates are not negative).
+struct TileRect {
+    int tx0, ty0, w, h;
+};
+__device__ __forceinline__ TileRect tile_rect(short4 b, int lw, int lh)
+{
+    TileRect r;
+    r.tx0 = b.x >> lw;
+    r.ty0 = b.z >> lh;
+    r.w = (b.y >> lw) - r.tx0 + 1;
+    r.h = (b.w >> lh) - r.ty0 + 1;
+    return r;
+}
+
+// floor(x / d) for 32-bit x and a divisor d >= 2 fixed for the launch, from
+// m = ceil(2^64 / d): x m / 2^64 exceeds x / d by less than 2^-32, which
+// cannot carry it past the next integer.
+struct Div32 {
+    uint64_t m;
+    bool one;  // d == 1
+};
+inline Div32 make_div32(uint32_t d)
+{
+    Div32 v;
+    v.one = d <= 1;
+    v.m = v.one ? 0 : (~0ull / d) + 1;  // floor((2^64 - 1) / d) + 1 = ceil(2^64 / d)
+    return v;
+}
+__device__ __forceinline__ uint32_t div32(uint32_t x, const Div32 &d) { return d.one ? x : (uint32_t)__umul64hi(x, d.m); }
+
+// Pair counts of the depth-ordered records: per block of 4096 records (16
+// consecutive ones per thread) into block_sum, and per group of 256 records
+// (one emission block) into group_sum.
+__global__ __launch_bounds__(kSortThreads) void count_pairs_kernel(const BinsHeader *bh, const short4 *sorted_box,
+                                                                   int lw, int lh, uint32_t *block_sum,
+                                                                   uint32_t *group_sum)
+{
+    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
+    const int64_t nvis = bh->overflow ? 0 : (int64_t)bh->n_vis;
+    const int64_t base = (int64_t)blockIdx.x * kCompactTile;
+    if (base >= nvis) return;  // uniform; its sums are never read
+    const int t = threadIdx.x;
+    const int64_t e0 = base + (int64_t)t * kCompactItems;
+    uint32_t cnt = 0;
+    if (e0 + kCompactItems <= nvis) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(sorted_box + e0);
+#pragma unroll
+        for (int q = 0; q < kCompactItems / 2; ++q) {
+            const uint4 u = src[q];  // two boxes
+            const short4 b0 = __builtin_bit_cast(short4, make_uint2(u.x, u.y));
+            const short4 b1 = __builtin_bit_cast(short4, make_uint2(u.z, u.w));
+            const TileRect r0 = tile_rect(b0, lw, lh), r1 = tile_rect(b1, lw, lh);
+            cnt += (uint32_t)(r0.w * r0.h + r1.w * r1.h);
+        }
+    } else {
+        for (int q = 0; q < kCompactItems; ++q)
+            if (e0 + q < nvis) {
+                const TileRect r = tile_rect(sorted_box[e0 + q], lw, lh);
+                cnt += (uint32_t)(r.w * r.h);
+            }
+    }
+    // groups of 256 records = 16 consecutive lanes
+    uint32_t g = cnt;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) g += __shfl_xor(g, off, 16);
+    if ((t & 15) == 0) group_sum[(int64_t)blockIdx.x * 16 + (t >> 4)] = g;
+    uint32_t total;
+    block_exclusive_scan(cnt, s_tmp, &total);
+    if (t == 0) block_sum[blockIdx.x] = total;
+}
+
+// Pair emission.  One block per 256 depth-ordered records: their tile counts
+// are scanned in the block; the block's first pair is its 4096-record block's
+// scanned offset plus the pairs of the groups before it.  Each wavefront
+// writes a contiguous range of the block's pairs, 64 consecutive pairs per
+// step (contiguous stores).  The record of each pair: the record holding the
+// step's first pair (a binary search at a wavefront's first step, then carried
+// over), plus the number of records that start at or before the pair within
+// the step (their start positions are flagged in LDS and read back as one
+// ballot).
+__global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, const uint32_t *sorted_rec,
+                                                         const short4 *sorted_box, const ViewDesc *views,
+                                                         Div32 n, int lw, int lh, const uint32_t *block_sum,
+                                                         const uint32_t *group_sum, uint32_t *pkeys,
+                                                         uint32_t *pvals)
+{
     __shared__ uint32_t s_off[257];
     __shared__ uint32_t s_rec[256], s_row0[256], s_tx[256];
     __shared__ uint16_t s_w[256];
+    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
+    __shared__ uint8_t s_flag[256 / kWave][kWave];
+    const int64_t nvis = bh->overflow ? 0 : (int64_t)bh->n_vis;  // nothing is emitted on overflow
     const int64_t j0 = (int64_t)blockIdx.x * 256;
-    const int64_t nvis = bh->n_vis;
-    if (bh->overflow || j0 >= nvis) return;  // uniform
+    if (j0 >= nvis) return;  // uniform
     const int cntb = nvis - j0 < 256 ? (int)(nvis - j0) : 256;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
+    uint32_t cnt = 0;
     if (t < cntb) {
         const uint32_t rec = sorted_rec[j0 + t];
-        const short4 b = sorted_box[j0 + t];
-        const ViewDesc &V = views[rec / n];
-        const int tx0 = b.x / tw, tx1 = b.y / tw, ty0 = b.z / th, ty1 = b.w / th;
-        const uint32_t off = pair_off[j0 + t];
-        s_off[t] = off;
+        const TileRect r = tile_rect(sorted_box[j0 + t], lw, lh);
+        const ViewDesc &V = views[div32(rec, n)];
+        cnt = (uint32_t)(r.w * r.h);
         s_rec[t] = rec;
-        s_row0[t] = (uint32_t)V.tile_offset + (uint32_t)(ty0 * V.tiles_x + tx0);
+        s_row0[t] = (uint32_t)V.tile_offset + (uint32_t)(r.ty0 * V.tiles_x + r.tx0);
         s_tx[t] = (uint32_t)V.tiles_x;
-        s_w[t] = (uint16_t)(tx1 - tx0 + 1);
-        if (t == cntb - 1) s_off[cntb] = off + (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        s_w[t] = (uint16_t)r.w;
     }
+    uint32_t total;
+    const uint32_t off = block_exclusive_scan(cnt, s_tmp, &total);
+    uint64_t base = block_sum[blockIdx.x >> 4];
+    for (unsigned gi = blockIdx.x & ~15u; gi < blockIdx.x; ++gi) base += group_sum[gi];
+    if (t < cntb) s_off[t] = off;
+    if (t == 0) s_off[cntb] = total;
     __syncthreads();
-    const uint32_t base = s_off[0], cap = bh->n_pairs;
-    const uint32_t total = s_off[cntb] - base;
-    for (uint32_t p = t; p < total; p += 256) {
-        const uint32_t gp = base + p;
-        if (gp >= cap) break;
-        int lo = 0, hi = cntb - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= gp) lo = mid; else hi = mid - 1;
+    const uint64_t cap = bh->n_pairs;  // pairs are only emitted below the binned count
+    const uint32_t nsteps = (total + kWave - 1) / kWave, per = (nsteps + 3) / 4;
+    const uint32_t c0 = w * per, c1 = c0 + per < nsteps ? c0 + per : nsteps;
+    int r_cur = -1;
+    const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+    for (uint32_t c = c0; c < c1; ++c) {
+        const uint32_t q0 = c * kWave;
+        int r0;
+        if (r_cur < 0) {  // the record holding pair q0 (wave-uniform)
+            int lo = 0, hi = cntb - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= q0) lo = mid; else hi = mid - 1;
+            }
+            r0 = lo;
+        } else {
+            r0 = (r_cur + 1 < cntb && s_off[r_cur + 1] <= q0) ? r_cur + 1 : r_cur;
         }
-        const uint32_t local = gp - s_off[lo], w = s_w[lo];
-        const uint32_t dy = local / w, dx = local - dy * w;
-        pkeys[gp] = s_row0[lo] + dy * s_tx[lo] + dx;
-        pvals[gp] = s_rec[lo];
+        s_flag[w][lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        const int idx = r0 + 1 + lane;
+        if (idx < cntb) {
+            const uint32_t d = s_off[idx] - q0;
+            if (d < (uint32_t)kWave) s_flag[w][d] = 1;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t starts = __ballot(s_flag[w][lane] != 0);
+        const int r = r0 + __popcll(starts & upto);
+        const uint32_t q = q0 + lane;
+        const uint64_t gp = base + q;
+        if (q < total && gp < cap) {
+            // (dy, dx) of the pair inside the record's tile rectangle: the quotient
+            // from the float reciprocal is off by at most one (local < 2^22)
+            const uint32_t local = q - s_off[r], wr = s_w[r];
+            uint32_t dy = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)wr));
+            int32_t rem = (int32_t)local - (int32_t)(dy * wr);
+            if (rem < 0) {
+                dy -= 1;
+                rem += (int32_t)wr;
+            } else if (rem >= (int32_t)wr) {
+                dy += 1;
+                rem -= (int32_t)wr;
+            }
+            pkeys[gp] = s_row0[r] + dy * s_tx[r] + (uint32_t)rem;
+            pvals[gp] = s_rec[r];
+        }
+        r_cur = __shfl(r, kWave - 1, kWave);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -581,7 +752,7 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     char *wb = (char *)work;
     uint32_t *keys_a = (uint32_t *)(wb + L.keys_a), *vals_a = (uint32_t *)(wb + L.vals_a);
     uint32_t *keys_b = (uint32_t *)(wb + L.keys_b), *vals_b = (uint32_t *)(wb + L.vals_b);
-    uint32_t *pair_off = (uint32_t *)(wb + L.pair_off);
+    uint32_t *block_sum = (uint32_t *)(wb + L.block_sum), *group_sum = (uint32_t *)(wb + L.group_sum);
     uint32_t *pkeys_a = (uint32_t *)(wb + L.pkeys_a), *pkeys_b = (uint32_t *)(wb + L.pkeys_b);
     uint32_t *pvals_b = (uint32_t *)(wb + L.pvals_b);
     uint32_t *hist = (uint32_t *)(wb + L.hist), *partials = (uint32_t *)(wb + L.partials);
@@ -596,9 +767,11 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
 
     // 1. compact visible records, then sort them by depth bits
     if (R > 0) {
-        e = device_scan(LoadVisible{P.ntiles}, StoreCompact{P.depth, keys_a, vals_a}, Count{&B.hdr->n_rec, R},
-                        partials, s);
-        if (e != hipSuccess) return e;
+        const int64_t nb = ceil_div(R, kCompactTile);
+        count_visible_kernel<<<(unsigned)nb, kSortThreads, 0, s>>>(B.hdr, P.ntiles, block_sum);
+        scan_partials_kernel<<<1, 1024, 0, s>>>(block_sum, nb, &B.hdr->n_rec, kCompactTile);
+        compact_visible_kernel<<<(unsigned)nb, kSortThreads, 0, s>>>(B.hdr, P.ntiles, P.depth, block_sum, keys_a,
+                                                                     vals_a);
     }
     const Count vis_cnt{&B.hdr->n_vis, R};
     bool depth_in_b = false;
@@ -616,11 +789,16 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     uint32_t *emit_vals = odd ? pvals_b : B.pair_rec;
     uint32_t *other_vals = odd ? B.pair_rec : pvals_b;
     if (R > 0 && cap > 0) {
-        e = device_scan(LoadTilesOfBox{sorted_box, tile_w, tile_h}, StoreArray{pair_off}, vis_cnt, partials, s);
-        if (e != hipSuccess) return e;
-        emit_pairs_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(B.hdr, sorted_rec, pair_off,
-                                                                     (const short4 *)sorted_box, P.views,
-                                                                     (uint32_t)n, tile_w, tile_h, pkeys_a, emit_vals);
+        const int64_t nb = ceil_div(R, kCompactTile);
+        int lw = 0, lh = 0;  // tile sides are powers of two
+        while ((1 << lw) < tile_w) ++lw;
+        while ((1 << lh) < tile_h) ++lh;
+        count_pairs_kernel<<<(unsigned)nb, kSortThreads, 0, s>>>(B.hdr, (const short4 *)sorted_box, lw, lh,
+                                                                 block_sum, group_sum);
+        scan_partials_kernel<<<1, 1024, 0, s>>>(block_sum, nb, &B.hdr->n_vis, kCompactTile);
+        emit_pairs_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(B.hdr, sorted_rec, (const short4 *)sorted_box,
+                                                                     P.views, make_div32((uint32_t)n), lw, lh, block_sum,
+                                                                     group_sum, pkeys_a, emit_vals);
         // 3. stable sort by global tile id
         bool pairs_in_b = false;
         const Count pair_cnt{&B.hdr->n_pairs, cap};
