@@ -64,8 +64,9 @@ TRAFFIC_SOURCES = ("paper_2501_18630_amd/csrc/raster.hip", "paper_2501_18630_amd
 
 def measured_traffic(workload: str):
     """HBM bytes per launch of the raster reverse pass from the committed
-    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when the summary
-    is for another workload or the kernel sources changed since it was taken."""
+    counter summary (TCC read and write requests weighted by their size, checked
+    against copies of known size), or None when the summary is for another
+    workload or the kernel sources changed since it was taken."""
     import hashlib
     try:
         fields = dict(line.split(": ", 1) for line in open(TRAFFIC_FILE).read().splitlines()
