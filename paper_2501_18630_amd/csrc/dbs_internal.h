@@ -117,13 +117,14 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // elements per block
 constexpr int kMaxRadixBits = 9;  // digits of 8 or 9 bits
 constexpr int kMaxRadix = 1 << kMaxRadixBits;
-constexpr int kScanTile = 4096;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+// Row stride of a radix pass's digit-major histogram over nblocks chunks.
+inline int64_t hist_stride(int64_t nblocks) { return (nblocks + 3) / 4 * 4; }
 
 struct WorkLayout {
     // bin/sort phase
-    size_t keys_a, vals_a, keys_b, vals_b, block_sum, group_sum, pkeys_a, pkeys_b, pvals_b, hist, partials,
+    size_t keys_a, vals_a, keys_b, vals_b, block_sum, group_sum, pkeys_a, pkeys_b, pvals_b, hist, totals,
         tkeys_a, tvals_a, tkeys_b, sorted_box, sort_total;
     size_t total;
     int64_t hist_blocks;  // max sort blocks of any sort
@@ -135,8 +136,7 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     if (cap > maxn) maxn = cap;
     if (n_tiles > maxn) maxn = n_tiles;
     L.hist_blocks = ceil_div(maxn > 0 ? maxn : 1, kSortTile);
-    size_t hist_n = (size_t)L.hist_blocks * kMaxRadix;
-    size_t part_n = (size_t)ceil_div((int64_t)(hist_n > R + 1 ? hist_n : R + 1), kScanTile) + 64;
+    size_t hist_n = (size_t)hist_stride(L.hist_blocks) * kMaxRadix;
     L.keys_a = o;   o = align_up(o + 4 * R);
     L.vals_a = o;   o = align_up(o + 4 * R);
     L.keys_b = o;   o = align_up(o + 4 * R);
@@ -149,7 +149,7 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     L.pkeys_b = o;  o = align_up(o + 4 * (size_t)cap);
     L.pvals_b = o;  o = align_up(o + 4 * (size_t)cap);
     L.hist = o;     o = align_up(o + 4 * hist_n);
-    L.partials = o; o = align_up(o + 4 * part_n);
+    L.totals = o;   o = align_up(o + 4 * (size_t)kMaxRadix);  // digit totals of a radix pass
     L.tkeys_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
     L.tvals_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
     L.tkeys_b = o;  o = align_up(o + 4 * (size_t)n_tiles);

@@ -314,8 +314,9 @@ __device__ __forceinline__ int build_list(const float4 *s_col, int nb, int w, ui
 
 // Splits a wave's block list into the lists of its four rows (quadrants), in
 // order: slot k goes to row r if its support reaches the quadrant and its list
-// position lo + k is at most lim[r].  rows: [4][BATCH]; counts returned in cnt.
-template <int BATCH>
+// position lo + k is at most lim[r].  Row r's list starts at rows[r * RS + PAD];
+// counts returned in cnt.
+template <int RS, int PAD>
 __device__ __forceinline__ void build_rows(const Staged &S, const uint8_t *blist, int cnt_b, int bx, int by,
                                            int64_t lo, const int32_t lim[4], uint8_t *rows, int cnt[4], int lane)
 {
@@ -335,7 +336,7 @@ __device__ __forceinline__ void build_rows(const Staged &S, const uint8_t *blist
             const bool in = valid && j <= lim[r] &&
                             !(rect_min_r2(fcx, fcy, f00, f01, f11, x0, x0 + 3.0f, y0, y0 + 3.0f) >= thr);
             const uint64_t bal = __ballot(in);
-            if (in) rows[r * BATCH + cnt[r] + __popcll(bal & lanes_below(lane))] = (uint8_t)k;
+            if (in) rows[r * RS + PAD + cnt[r] + __popcll(bal & lanes_below(lane))] = (uint8_t)k;
             cnt[r] += __popcll(bal);
         }
     }
@@ -353,7 +354,7 @@ __device__ __forceinline__ int max4(const int v[4]) { return max(max(v[0], v[1])
 // their sums are merged first and only the lowest such row stores.  Bit
 // 4e + r of share[s], e = 0/1/2: row r's splat is also that of row r^(e+1);
 // bit 12 + r: another, lower row stores for row r.  Zero: no two rows share.
-template <int BATCH>
+template <int RS, int PAD>
 __device__ __forceinline__ void mark_shared_steps(const uint8_t *rows, const int cnt[4], int steps, uint16_t *share,
                                                   int lane)
 {
@@ -363,7 +364,7 @@ __device__ __forceinline__ void mark_shared_steps(const uint8_t *rows, const int
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int t = cnt[r] - 1 - st;
-            kk[r] = (st < steps && t >= 0) ? (int)rows[r * BATCH + t] : -1 - r;
+            kk[r] = (st < steps && t >= 0) ? (int)rows[r * RS + PAD + t] : -1 - r;
         }
         uint32_t word = 0;
 #pragma unroll
@@ -420,7 +421,7 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
             for (int r = 0; r < 4; ++r) lim[r] = ((live >> (16 * r)) & 0xffffull) ? INT32_MAX : -1;
             const int cnt_b = live ? build_list(s_col, nb, w, s_blist[w], lane) : 0;
             int cnt[4];
-            build_rows<BATCH>(S, s_blist[w], cnt_b, P.bx, P.by, (int64_t)start, lim, s_rows[w], cnt, lane);
+            build_rows<BATCH, 0>(S, s_blist[w], cnt_b, P.bx, P.by, (int64_t)start, lim, s_rows[w], cnt, lane);
             const int my_cnt = pick4(cnt, P.row), steps = max4(cnt);
             for (int t = 0; t < steps; ++t) {
                 const bool act = t < my_cnt && !done;
@@ -497,13 +498,20 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
     using G = Geo<TW, TH>;
     constexpr int NT = G::NT;
     constexpr int NG = 10;
-    static_assert(BATCH <= 256, "list entries are 8-bit");
-    __shared__ double2 s_c[BATCH], s_a[BATCH], s_b[BATCH];
-    __shared__ float4 s_col[BATCH];
+    static_assert(BATCH < 256, "list entries are 8-bit, slot BATCH is the sentinel");
+    // Slot BATCH holds a sentinel splat that reaches no pixel.  PAD sentinel
+    // entries precede each row's list, so that a row whose list is exhausted
+    // keeps taking valid entries (and contributes nothing) while the other
+    // rows of its wavefront step on: the step loop needs no per-lane bounds.
+    constexpr int PAD = BATCH + 4, RS = PAD + BATCH;
+    __shared__ double2 s_c[BATCH + 1], s_a[BATCH + 1], s_b[BATCH + 1];
+    __shared__ float4 s_col[BATCH + 1];
     __shared__ uint32_t s_rec[BATCH];
-    __shared__ __align__(16) float s_g[G::NW][BATCH][NG];  // per-wave sums; wave 0's slot ends up with the total
+    // per-wave sums (slot BATCH: the sentinel's; one more slot keeps the array a whole number of float4s);
+    // wave 0's slot ends up with the total
+    __shared__ __align__(16) float s_g[G::NW][BATCH + 2][NG];
     __shared__ uint8_t s_blist[G::NW][BATCH];
-    __shared__ uint8_t s_rows[G::NW][4 * BATCH];
+    __shared__ uint8_t s_rows[G::NW][4 * RS];
     __shared__ uint16_t s_share[G::NW][BATCH];
     __shared__ Item s_item;
     __shared__ int32_t s_maxlast;
@@ -511,7 +519,15 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const LanePixel<TW, TH> P(w, lane);
     const double fpx = (double)P.lx + 0.5, fpy = (double)P.ly + 0.5;
-    const uint8_t *my_row = &s_rows[w][P.row * BATCH];
+    const uint8_t *my_row = &s_rows[w][P.row * RS + PAD];
+    // written once; the first work item's barrier orders them before any use
+    if (tid == 0) {
+        s_c[BATCH] = make_double2(1e30, 1e30);  // r^2 ~ 1e60 at every pixel
+        s_a[BATCH] = make_double2(1.0, 0.0);
+        s_b[BATCH] = make_double2(1.0, pack2(0.0f, 1.0f));
+        s_col[BATCH] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    for (int i = lane; i < 4 * PAD; i += kWave) s_rows[w][(i / PAD) * RS + i % PAD] = (uint8_t)BATCH;
     const float kLn2 = 0.69314718055994531f;
     const int fld = row10_field(lane);  // value whose row total this lane stores
     uint32_t n_atomics = 0;  // COUNT only
@@ -553,8 +569,8 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                 const int64_t lo = hi - BATCH > (int64_t)it.start ? hi - BATCH : (int64_t)it.start;
                 const int nb = (int)(hi - lo);
                 stage<TW, TH, false>(a, (uint32_t)lo, nb, (double)it.ox, (double)it.oy, S, tid);
-                static_assert((G::NW * BATCH * NG) % 4 == 0, "slots are cleared in float4s");
-                for (int idx = tid; idx < G::NW * BATCH * NG / 4; idx += NT)
+                static_assert(sizeof(s_g) % 16 == 0, "slots are cleared in float4s");
+                for (int idx = tid; idx < (int)(sizeof(s_g) / 16); idx += NT)
                     reinterpret_cast<float4 *>(&s_g[0][0][0])[idx] = make_float4(0.f, 0.f, 0.f, 0.f);
                 __syncthreads();
                 // this wave only needs its own splats up to its last contributor
@@ -565,26 +581,26 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                 const int last_k = lk64 < 0 ? -1 : (lk64 > (int64_t)BATCH ? BATCH : (int)lk64);
                 const int cnt_b = nbw > 0 ? build_list(s_col, nbw, w, s_blist[w], lane) : 0;
                 int cnt[4];
-                build_rows<BATCH>(S, s_blist[w], cnt_b, P.bx, P.by, lo, row_last, s_rows[w], cnt, lane);
+                build_rows<RS, PAD>(S, s_blist[w], cnt_b, P.bx, P.by, lo, row_last, s_rows[w], cnt, lane);
                 // wave-uniform (ballot counts): a scalar loop bound and counter
                 const int my_cnt = pick4(cnt, P.row), steps = __builtin_amdgcn_readfirstlane(max4(cnt));
-                mark_shared_steps<BATCH>(s_rows[w], cnt, steps, s_share[w], lane);
-                // list entries are read one step ahead
-                int kl_next = my_row[my_cnt > 0 ? my_cnt - 1 : 0];  // in bounds either way
+                mark_shared_steps<RS, PAD>(s_rows[w], cnt, steps, s_share[w], lane);
+                // list entries are read one step ahead, back to front; past the
+                // front (t < 0, down to -steps - 1 >= -PAD) they are the sentinel
+                int kl_next = my_row[my_cnt - 1];
                 for (int step = 0; step < steps; ++step) {
-                    const int t = my_cnt - 1 - step;  // back to front
-                    const bool has = t >= 0;
-                    const int k = has ? kl_next : 0;
-                    kl_next = my_row[t > 0 ? t - 1 : 0];
-                    const bool owner = fld >= 0 && has;
-                    float *dst = &s_g[w][k][fld < 0 ? 0 : fld];
+                    const int t = my_cnt - 1 - step;
+                    const int k = kl_next;
+                    kl_next = my_row[t - 1];
+                    const bool owner = fld >= 0;
+                    float *dst = &s_g[w][k][owner ? fld : 0];
                     // read early: the slot's running sum, added to at the end of the step
-                    const float prev = owner ? *dst : 0.0f;
+                    const float prev = *dst;
                     const uint32_t share = __builtin_amdgcn_readfirstlane(s_share[w][step]);
                     const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
                     const double dxd = fpx - c.x, dyd = fpy - c.y;
                     const double r2 = eval_r2(dxd, dyd, aa.x, aa.y, bb.x);
-                    const bool contrib = has && k <= last_k && r2 < 1.0;
+                    const bool contrib = k <= last_k && r2 < 1.0;
                     if (!__ballot(contrib)) continue;
                     // Branch-free from here: a lane that does not take part uses
                     // r^2 = 0 (finite logs) and alpha = 0 (T, S unchanged), and
@@ -769,7 +785,7 @@ __global__ __launch_bounds__(TW *TH) void raster_wave_stats_kernel(RasterArgs a,
         const int nbw = kmax64 < (int64_t)(nb - 1) ? (int)kmax64 + 1 : nb;
         const int cnt_b = nbw > 0 ? build_list(s_col, nbw, w, s_blist[w], lane) : 0;
         int cnt[4];
-        build_rows<BATCH>(S, s_blist[w], cnt_b, P.bx, P.by, lo, row_last, s_rows[w], cnt, lane);
+        build_rows<BATCH, 0>(S, s_blist[w], cnt_b, P.bx, P.by, lo, row_last, s_rows[w], cnt, lane);
         const int my_cnt = pick4(cnt, P.row), steps = max4(cnt);
         for (int step = 0; step < steps; ++step) {
             const int t = my_cnt - 1 - step;

@@ -14,8 +14,8 @@
 // order, at 2-3 narrow passes over the K pairs instead of 6-7 wide ones.
 //
 // The radix sort is a classic LSD sort with 8-bit digits: per-block digit
-// histograms (upsweep), a device-wide exclusive scan of the digit-major
-// histogram, and a stable scatter (downsweep) that ranks each block's keys
+// histograms (upsweep), a scan of each digit's counts over the blocks plus
+// the digit totals, and a stable scatter (downsweep) that ranks each block's keys
 // with wave ballots and per-wave digit counts in LDS (no LDS atomics, one
 // barrier per phase) and writes them out digit-contiguous.  Element counts
 // are read from device memory, so the whole pipeline runs without a host
@@ -47,9 +47,9 @@ __device__ inline uint64_t lanemask_lt()
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
-// Exclusive scan of one value per thread across a block of kSortThreads.
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp /*[kSortThreads/kWave + 1]*/,
-                                                uint32_t *total)
+// Exclusive scan of one value per thread across a block of NT threads.
+template <int NT = kSortThreads>
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp /*[NT/kWave + 1]*/, uint32_t *total)
 {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     uint32_t x = v;
@@ -62,40 +62,21 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp /*[k
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t acc = 0;
-        for (int k = 0; k < kSortThreads / kWave; ++k) {
+        for (int k = 0; k < NT / kWave; ++k) {
             uint32_t c = s_tmp[k];
             s_tmp[k] = acc;
             acc += c;
         }
-        s_tmp[kSortThreads / kWave] = acc;
+        s_tmp[NT / kWave] = acc;
     }
     __syncthreads();
     uint32_t r = s_tmp[w] + x - v;
-    if (total) *total = s_tmp[kSortThreads / kWave];
+    if (total) *total = s_tmp[NT / kWave];
     __syncthreads();
     return r;
 }
 
-// ---------------------------------------------------------------- device-wide scan
-// Exclusive scan of Load(i), i < n, in tiles of kScanTile = 256 threads x 16
-// items (blocked per thread); Store(i, prefix, value) receives the result.
-
-template <class Load>
-__global__ __launch_bounds__(kSortThreads) void scan_reduce_kernel(Load ld, Count cnt, uint32_t *partials)
-{
-    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
-    const int64_t n = cnt.get();
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
-    uint32_t acc = 0;
-#pragma unroll 4
-    for (int k = 0; k < 16; ++k) {
-        const int64_t e = base + (int64_t)k * kSortThreads;  // striped: coalesced
-        if (e < n) acc += ld(e);
-    }
-    uint32_t total;
-    block_exclusive_scan(acc, s_tmp, &total);
-    if (threadIdx.x == 0) partials[blockIdx.x] = total;
-}
+// ---------------------------------------------------------------- scans
 
 // Single-block exclusive scan of partials[0..nb), in place.  With `items`
 // set, only the ceil(*items / per_block) partials of blocks that hold items
@@ -139,66 +120,61 @@ __global__ __launch_bounds__(1024) void scan_partials_kernel(uint32_t *partials,
     }
 }
 
-// Values are loaded striped (coalesced), transposed through LDS so that each
-// thread scans 16 consecutive elements, and the prefixes are handed back in
-// striped order to the store.
-__device__ __forceinline__ int scan_pad(int e) { return e + (e >> 4); }
-
-template <class Load, class Store>
-__global__ __launch_bounds__(kSortThreads) void scan_apply_kernel(Load ld, Store st, Count cnt,
-                                                                  const uint32_t *partials)
+// Exclusive scan of each digit's row of the digit-major histogram of a radix
+// pass, over the blocks that hold keys, in place; workgroup d also writes the
+// digit's total.  Row d is contiguous and starts on 16 bytes (the row stride
+// is a multiple of 4); each of kDigitScanThreads threads scans 16 consecutive
+// entries of a tile, moved as four 16-byte loads and stores.
+constexpr int kDigitScanThreads = 1024;
+__global__ __launch_bounds__(kDigitScanThreads) void scan_digits_kernel(uint32_t *hist, int64_t hstride, Count cnt,
+                                                                        uint32_t *totals)
 {
-    __shared__ uint32_t s_v[kScanTile + kScanTile / 16];
-    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
+    __shared__ uint32_t s_tmp[kDigitScanThreads / kWave + 1];
     const int64_t n = cnt.get();
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    const int t = threadIdx.x;
-    uint32_t v[16];
+    const int64_t nb_used = (n + kSortTile - 1) / kSortTile;
+    uint32_t *row = hist + (int64_t)blockIdx.x * hstride;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nb_used; base += 16 * kDigitScanThreads) {  // uniform
+        const int64_t e0 = base + (int64_t)threadIdx.x * 16;
+        const bool whole = e0 + 16 <= nb_used;
+        uint32_t v[16], acc = 0;
+        if (whole) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(row + e0);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int e = k * kSortThreads + t;
-        v[k] = base + e < n ? ld(base + e) : 0u;
-        s_v[scan_pad(e)] = v[k];
-    }
-    __syncthreads();
-    uint32_t loc[16], acc = 0;
+            for (int q = 0; q < 4; ++q) {
+                const uint4 u = src[q];
+                v[4 * q] = u.x;
+                v[4 * q + 1] = u.y;
+                v[4 * q + 2] = u.z;
+                v[4 * q + 3] = u.w;
+            }
+        } else {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        loc[k] = s_v[scan_pad(t * 16 + k)];
-        acc += loc[k];
-    }
-    uint32_t pre = block_exclusive_scan(acc, s_tmp, nullptr) + partials[blockIdx.x];
+            for (int k = 0; k < 16; ++k) v[k] = e0 + k < nb_used ? row[e0 + k] : 0u;
+        }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        s_v[scan_pad(t * 16 + k)] = pre;
-        pre += loc[k];
-    }
-    __syncthreads();
+        for (int k = 0; k < 16; ++k) acc += v[k];
+        uint32_t total;
+        uint32_t pre = carry + block_exclusive_scan<kDigitScanThreads>(acc, s_tmp, &total);
+        uint32_t o[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int e = k * kSortThreads + t;
-        if (base + e < n) st(base + e, s_v[scan_pad(e)], v[k]);
+        for (int k = 0; k < 16; ++k) {
+            o[k] = pre;
+            pre += v[k];
+        }
+        if (whole) {
+            uint4 *dst = reinterpret_cast<uint4 *>(row + e0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (e0 + k < nb_used) row[e0 + k] = o[k];
+        }
+        carry += total;
     }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
-
-template <class Load, class Store>
-hipError_t device_scan(Load ld, Store st, Count cnt, uint32_t *partials, hipStream_t s)
-{
-    const int64_t nb = ceil_div(cnt.host > 0 ? cnt.host : 1, kScanTile);
-    scan_reduce_kernel<Load><<<(unsigned)nb, kSortThreads, 0, s>>>(ld, cnt, partials);
-    scan_partials_kernel<<<1, 1024, 0, s>>>(partials, nb);
-    scan_apply_kernel<Load, Store><<<(unsigned)nb, kSortThreads, 0, s>>>(ld, st, cnt, partials);
-    return hipGetLastError();
-}
-
-struct LoadArray {
-    const uint32_t *a;
-    __device__ uint32_t operator()(int64_t i) const { return a[i]; }
-};
-struct StoreArray {
-    uint32_t *a;
-    __device__ void operator()(int64_t i, uint32_t pre, uint32_t) const { a[i] = pre; }
-};
 
 // ---------------------------------------------------------------- radix sort
 
@@ -245,7 +221,7 @@ __device__ __forceinline__ int64_t sort_elem(int64_t block_base, int w, int k, i
 
 template <int RB>
 __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint32_t *keys, Count cnt, int shift,
-                                                                     int width, uint32_t *hist, int64_t nblocks)
+                                                                     int width, uint32_t *hist, int64_t hstride)
 {
     // UC count rows per wave, lane l adding into row l % UC: equal digits of
     // one wave then collide UC times less, and the odd row stride puts the
@@ -280,17 +256,26 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
         uint32_t tot = 0;
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) tot += s_cnt[r * STRIDE + dd];
-        hist[(int64_t)dd * nblocks + chunk] = tot;
+        hist[(int64_t)dd * hstride + chunk] = tot;
     }
 }
 
-// If gather_src is set, also writes gather_out[o] = gather_src[value] at each
-// output position o (used to carry a per-value field through the last pass).
+// The output offset of digit d of this chunk is the digit's base (the
+// exclusive scan of the digit totals) plus the chunk's entry of the
+// per-digit scanned histogram.  The last pass writes no keys (they are not
+// needed afterwards).  In the last pass, if gather_src is set, it also writes
+// gather_out[o] = gather_src[value] at each output position o (a per-value
+// field carried through the sort), and if ranges is set (a sort by the full
+// key, ranges[] holding (~0, 0) before), each key's output range
+// [start, end) is recorded in ranges[key]: a block's equal keys are
+// contiguous in its LDS-sorted order and in the output, and the blocks'
+// pieces of a key's range are merged with atomic min / max.
 template <int RB>
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
-    uint32_t *__restrict__ vals_out, Count cnt, int shift, int width, const uint32_t *hist, int64_t nblocks,
-    const uint2 *__restrict__ gather_src, uint2 *__restrict__ gather_out)
+    uint32_t *__restrict__ vals_out, Count cnt, int shift, int width, const uint32_t *hist,
+    const uint32_t *totals, int64_t hstride, const uint2 *__restrict__ gather_src, uint2 *__restrict__ gather_out,
+    uint2 *ranges, bool last)
 {
     constexpr int NW = kSortThreads / kWave, RADIX = 1 << RB, DPT = RADIX / kSortThreads;
     __shared__ uint32_t s_keys[kSortTile];
@@ -307,12 +292,22 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const int64_t base = chunk * kSortTile;
     if (base >= n) return;  // uniform across the block
     const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
+    {   // thread t owns digits t * DPT .. t * DPT + DPT - 1
+        uint32_t tot[DPT], sum = 0;
 #pragma unroll
-    for (int q = 0; q < DPT; ++q) {
-        const int dd = q * kSortThreads + t;
-        s_goff[dd] = hist[(int64_t)dd * nblocks + chunk];
+        for (int q = 0; q < DPT; ++q) {
+            tot[q] = totals[t * DPT + q];
+            sum += tot[q];
+        }
+        uint32_t st = block_exclusive_scan(sum, s_tmp, nullptr);
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) s_wh[ww][dd] = 0;
+        for (int q = 0; q < DPT; ++q) {
+            const int dd = t * DPT + q;
+            s_goff[dd] = st + hist[(int64_t)dd * hstride + chunk];
+            st += tot[q];
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) s_wh[ww][dd] = 0;
+        }
     }
     __syncthreads();
 
@@ -374,23 +369,32 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
         const uint32_t d = (kk >> shift) & dmask;
         const uint32_t o = s_goff[d] + (uint32_t)j - s_start[d];
         const uint32_t vv = s_vals[j];
-        keys_out[o] = kk;
+        if (!last) keys_out[o] = kk;
         vals_out[o] = vv;
-        if (gather_src) gather_out[o] = gather_src[vv];
+        if (last && gather_src) gather_out[o] = gather_src[vv];
+        if (last && ranges) {
+            if (j == 0 || s_keys[j - 1] != kk) atomicMin(&ranges[kk].x, o);
+            if (j == cnt_blk - 1 || s_keys[j + 1] != kk) atomicMax(&ranges[kk].y, o + 1);
+        }
     }
 }
 
 int radix_passes(int bits) { return (bits + kMaxRadixBits - 1) / kMaxRadixBits; }
 
 // Stable sort of (keys, vals) by key bits [bit_lo, bit_hi); ping-pongs
-// between the a and b buffers and reports where the result ended up.  The
-// bits are split into radix_passes() digits of at most kMaxRadixBits, as
-// even as possible (17 bits: 9 + 8, not 8 + 8 + 1).
+// between the a and b buffers and reports where the values ended up (the
+// sorted keys are not kept: the last pass writes values only).  The bits are
+// split into radix_passes() digits of at most kMaxRadixBits, as even as
+// possible (17 bits: 9 + 8, not 8 + 8 + 1).  Each pass: per-chunk digit
+// counts, a per-digit scan over the chunks (with the digit totals in
+// `totals`, kMaxRadix entries), and the stable scatter.  gather_* and ranges
+// apply to the last pass (see radix_downsweep_kernel).
 hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Count cnt, int bit_lo,
-                      int bit_hi, uint32_t *hist, uint32_t *partials, hipStream_t s, bool *result_in_b,
-                      const uint2 *gather_src = nullptr, uint2 *gather_out = nullptr)
+                      int bit_hi, uint32_t *hist, uint32_t *totals, hipStream_t s, bool *result_in_b,
+                      const uint2 *gather_src = nullptr, uint2 *gather_out = nullptr, uint2 *ranges = nullptr)
 {
     const int64_t nblocks = ceil_div(cnt.host > 0 ? cnt.host : 1, kSortTile);
+    const int64_t hstride = hist_stride(nblocks);  // histogram rows start on 16 bytes
     const int bits = bit_hi - bit_lo, passes = radix_passes(bits);
     bool in_b = false;
     int shift = bit_lo;
@@ -398,29 +402,27 @@ hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Co
         const int width = (bits - (shift - bit_lo) + (passes - p) - 1) / (passes - p);
         const uint32_t *kin = in_b ? kb : ka, *vin = in_b ? vb : va;
         uint32_t *kout = in_b ? ka : kb, *vout = in_b ? va : vb;
-        const bool final_pass = p == passes - 1;
-        const int64_t nh = nblocks * ((int64_t)1 << width);
-        if (width <= 8)
-            radix_upsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, nblocks);
-        else
-            radix_upsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, nblocks);
-        hipError_t e = device_scan(LoadArray{hist}, StoreArray{hist}, Count{nullptr, nh}, partials, s);
-        if (e != hipSuccess) return e;
-        const uint2 *gs = final_pass ? gather_src : nullptr;
-        uint2 *go = final_pass ? gather_out : nullptr;
-        if (width <= 8)
-            radix_downsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, cnt, shift,
-                                                                                width, hist, nblocks, gs, go);
-        else
-            radix_downsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, cnt, shift,
-                                                                                width, hist, nblocks, gs, go);
+        const bool last = p == passes - 1;
+        const uint2 *gs = last ? gather_src : nullptr;
+        uint2 *go = last ? gather_out : nullptr;
+        uint2 *rg = last ? ranges : nullptr;
+        if (width <= 8) {
+            radix_upsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, hstride);
+            scan_digits_kernel<<<1u << 8, kDigitScanThreads, 0, s>>>(hist, hstride, cnt, totals);
+            radix_downsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+                kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg, last);
+        } else {
+            radix_upsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, hstride);
+            scan_digits_kernel<<<1u << 9, kDigitScanThreads, 0, s>>>(hist, hstride, cnt, totals);
+            radix_downsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+                kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg, last);
+        }
         in_b = !in_b;
         shift += width;
     }
     *result_in_b = in_b;
     return hipGetLastError();
 }
-
 
 // ---------------------------------------------------------------- binning kernels
 
@@ -694,43 +696,25 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t count, uint32_t value)
     if (i < count) p[i] = value;
 }
 
-// Tile ranges from the sorted keys: 4096 keys per workgroup staged in LDS
-// with one neighbour on each side; a range starts (ends) where a key differs
-// from its predecessor (successor).
-__global__ __launch_bounds__(256) void tile_ranges_kernel(const BinsHeader *bh, const uint32_t *skeys,
-                                                          uint2 *ranges)
+// Tile ranges before the last pass of the pair sort records them: (~0, 0),
+// so that atomic min / max leave (first, last + 1) of each listed tile.
+__global__ void fill_ranges_kernel(uint2 *ranges, int64_t n_tiles)
 {
-    __shared__ uint32_t s_k[4096 + 2];
-    const int64_t K = bh->n_pairs;
-    const int64_t base = (int64_t)blockIdx.x * 4096;
-    if (base >= K) return;  // uniform
-    const int t = threadIdx.x;
-    const int cnt = K - base < 4096 ? (int)(K - base) : 4096;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int e = k * 256 + t;
-        s_k[1 + e] = e < cnt ? skeys[base + e] : 0xffffffffu;
-    }
-    if (t == 0) s_k[0] = base > 0 ? skeys[base - 1] : 0xffffffffu;
-    if (t == 1) s_k[1 + cnt] = base + cnt < K ? skeys[base + cnt] : 0xffffffffu;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int e = k * 256 + t;
-        if (e < cnt) {
-            const uint32_t key = s_k[1 + e];
-            if (s_k[e] != key) ranges[key].x = (uint32_t)(base + e);
-            if (s_k[2 + e] != key) ranges[key].y = (uint32_t)(base + e + 1);
-        }
-    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_tiles) ranges[i] = make_uint2(0xffffffffu, 0u);
 }
 
-// Heaviest tiles first: key = 0xffff - min(pairs, 0xffff).
-__global__ void tile_cost_keys_kernel(const uint2 *ranges, int64_t n_tiles, uint32_t *keys, uint32_t *vals)
+// Heaviest tiles first: key = 0xffff - min(pairs, 0xffff).  Also turns the
+// range of a tile no pair reached, still (~0, 0), into (0, 0).
+__global__ void tile_cost_keys_kernel(uint2 *ranges, int64_t n_tiles, uint32_t *keys, uint32_t *vals)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
-    const uint2 r = ranges[t];
+    uint2 r = ranges[t];
+    if (r.x == 0xffffffffu) {
+        r = make_uint2(0u, 0u);
+        ranges[t] = r;
+    }
     const uint32_t c = r.y - r.x;
     keys[t] = 0xffffu - (c < 0xffffu ? c : 0xffffu);
     vals[t] = (uint32_t)t;
@@ -755,7 +739,7 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     uint32_t *block_sum = (uint32_t *)(wb + L.block_sum), *group_sum = (uint32_t *)(wb + L.group_sum);
     uint32_t *pkeys_a = (uint32_t *)(wb + L.pkeys_a), *pkeys_b = (uint32_t *)(wb + L.pkeys_b);
     uint32_t *pvals_b = (uint32_t *)(wb + L.pvals_b);
-    uint32_t *hist = (uint32_t *)(wb + L.hist), *partials = (uint32_t *)(wb + L.partials);
+    uint32_t *hist = (uint32_t *)(wb + L.hist), *totals = (uint32_t *)(wb + L.totals);
     uint32_t *tkeys_a = (uint32_t *)(wb + L.tkeys_a), *tvals_tmp = (uint32_t *)(wb + L.tvals_a);
     uint32_t *tkeys_b = (uint32_t *)(wb + L.tkeys_b);
     uint2 *sorted_box = (uint2 *)(wb + L.sorted_box);
@@ -777,14 +761,15 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     bool depth_in_b = false;
     if (R > 0) {
         // the last pass also writes each sorted record's pixel box contiguously
-        e = radix_sort(keys_a, vals_a, keys_b, vals_b, vis_cnt, 0, 32, hist, partials, s, &depth_in_b,
+        e = radix_sort(keys_a, vals_a, keys_b, vals_b, vis_cnt, 0, 32, hist, totals, s, &depth_in_b,
                        (const uint2 *)P.bbox, sorted_box);
         if (e != hipSuccess) return e;
     }
     const uint32_t *sorted_rec = depth_in_b ? vals_b : vals_a;
 
     // 2. pair offsets in depth order, emit (tile, record) pairs
-    const int tile_bits = bits_for(n_tiles);
+    // at least one pass, whose scatter records the tile ranges (one tile: a 1-bit pass of zero keys)
+    const int tile_bits = bits_for(n_tiles) > 0 ? bits_for(n_tiles) : 1;
     const bool odd = radix_passes(tile_bits) % 2 == 1;
     uint32_t *emit_vals = odd ? pvals_b : B.pair_rec;
     uint32_t *other_vals = odd ? B.pair_rec : pvals_b;
@@ -799,16 +784,14 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
         emit_pairs_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(B.hdr, sorted_rec, (const short4 *)sorted_box,
                                                                      P.views, make_div32((uint32_t)n), lw, lh, block_sum,
                                                                      group_sum, pkeys_a, emit_vals);
-        // 3. stable sort by global tile id
+        // 3. stable sort by global tile id; its last pass records the tile ranges
+        if (n_tiles > 0)
+            fill_ranges_kernel<<<(unsigned)ceil_div(n_tiles, 256), 256, 0, s>>>(B.tile_range, n_tiles);
         bool pairs_in_b = false;
         const Count pair_cnt{&B.hdr->n_pairs, cap};
-        e = radix_sort(pkeys_a, emit_vals, pkeys_b, other_vals, pair_cnt, 0, tile_bits, hist, partials, s,
-                       &pairs_in_b);
+        e = radix_sort(pkeys_a, emit_vals, pkeys_b, other_vals, pair_cnt, 0, tile_bits, hist, totals, s,
+                       &pairs_in_b, nullptr, nullptr, B.tile_range);
         if (e != hipSuccess) return e;
-        const uint32_t *skeys = pairs_in_b ? pkeys_b : pkeys_a;
-        fill_u32_kernel<<<(unsigned)ceil_div(2 * n_tiles, 256), 256, 0, s>>>((uint32_t *)B.tile_range,
-                                                                             2 * n_tiles, 0u);
-        tile_ranges_kernel<<<(unsigned)ceil_div(cap, 4096), 256, 0, s>>>(B.hdr, skeys, B.tile_range);
     } else {
         fill_u32_kernel<<<(unsigned)ceil_div(2 * n_tiles, 256), 256, 0, s>>>((uint32_t *)B.tile_range,
                                                                              2 * n_tiles, 0u);
@@ -819,7 +802,7 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
                                                                                B.tile_order);
         bool in_b = false;
         e = radix_sort(tkeys_a, B.tile_order, tkeys_b, tvals_tmp, Count{nullptr, n_tiles}, 0, 16, hist,
-                       partials, s, &in_b);
+                       totals, s, &in_b);
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();
