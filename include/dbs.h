@@ -274,9 +274,12 @@ dbs_status dbs_render_bwd(const dbs_splats *splats /*[host] struct of device poi
  * (mu', conic, o, b, colour) inside `projected`; dbs_project_bwd chains them
  * to the parameters (Sec. 3.2 projection, Sec. 3.3 Eq. 8), ADDS into *grads
  * and clears the accumulator.  dbs_render_bwd = dbs_raster_bwd, then
- * dbs_project_bwd.  dbs_project_bwd reads only the accumulator of records
- * the last dbs_preprocess left visible (ntiles > 0), so it must follow
- * dbs_raster_bwd without a dbs_preprocess on the same `projected` in between. */
+ * dbs_project_bwd.  dbs_raster_bwd also marks, in a per-record bit mask kept
+ * beside the accumulator, every record it sends gradient to; dbs_project_bwd
+ * reads only the marked records' accumulators and clears them with their
+ * marks.  It chains them through the projection of the last dbs_preprocess,
+ * so it must follow dbs_raster_bwd without a dbs_preprocess on the same
+ * `projected` in between. */
 dbs_status dbs_raster_bwd(const void *projected, const void *bins, const dbs_camera *cams /*[host]*/,
                           int32_t n_views, const dbs_raster_cfg *cfg /*[host]*/, int64_t n,
                           const float *final_T, const int32_t *last_index, const float *dL_dimage,

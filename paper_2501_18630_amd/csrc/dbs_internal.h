@@ -78,7 +78,7 @@ struct alignas(64) RasterRec {
 static_assert(sizeof(RasterRec) == 64, "RasterRec layout");
 
 struct ProjLayout {
-    size_t header, views, rec, bbox, depth, ntiles, vismask, sgrad, total;
+    size_t header, views, rec, bbox, depth, ntiles, gradmask, sgrad, total;
 };
 inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     ProjLayout L;
@@ -89,7 +89,7 @@ inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     L.bbox = o;   o = align_up(o + 8 * R);
     L.depth = o;  o = align_up(o + 4 * R);
     L.ntiles = o; o = align_up(o + 4 * R);
-    L.vismask = o; o = align_up(o + 8 * (size_t)n * (size_t)((n_views + 63) / 64));
+    L.gradmask = o; o = align_up(o + 8 * (size_t)n * (size_t)((n_views + 63) / 64));
     L.sgrad = o;  o = align_up(o + 64 * R);   // screen-space gradient, one 64-byte line per record
     L.total = o;
     return L;
@@ -194,7 +194,9 @@ struct ProjPtrs {
     RasterRec *rec;
     short4 *bbox;
     uint32_t *depth, *ntiles;
-    uint64_t *vismask;  // [(V+63)/64][n]: bit v%64 of word v/64 set when record (v, i) has ntiles > 0
+    // [(V+63)/64][n]: bit v%64 of word v/64 set when the raster reverse pass has
+    // sent gradient to record (v, i)'s line of sgrad; cleared with the line
+    uint64_t *gradmask;
     float4 *sgrad;  // [R][4]: dmu'(2), dA(3), do, db, dcolour(3), 6 unused
 };
 inline ProjPtrs proj_ptrs(void *base, int64_t n, int32_t n_views) {
@@ -207,7 +209,7 @@ inline ProjPtrs proj_ptrs(void *base, int64_t n, int32_t n_views) {
     p.bbox = (short4 *)(b + L.bbox);
     p.depth = (uint32_t *)(b + L.depth);
     p.ntiles = (uint32_t *)(b + L.ntiles);
-    p.vismask = (uint64_t *)(b + L.vismask);
+    p.gradmask = (uint64_t *)(b + L.gradmask);
     p.sgrad = (float4 *)(b + L.sgrad);
     return p;
 }

@@ -196,7 +196,6 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
         }
         ok = ok && fin;
 
-        uint64_t vm = 0;
         for (int32_t v = 0; v < n_views; ++v) {
             const ViewDesc &V = P.views[v];
             const int64_t rec = (int64_t)v * n + i;
@@ -318,12 +317,6 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
             }
             P.bbox[rec] = bb;
             P.ntiles[rec] = ntiles;
-            // per-splat visibility bits, read by the reverse pass to skip culled records
-            vm |= (uint64_t)(ntiles > 0) << (v & 63);
-            if ((v & 63) == 63 || v == n_views - 1) {
-                P.vismask[(int64_t)(v >> 6) * n + i] = vm;
-                vm = 0;
-            }
         }
     }
     vis = wave_sum_u64(vis);

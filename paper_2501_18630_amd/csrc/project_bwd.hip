@@ -3,8 +3,10 @@
 // Input: per-record screen-space gradients accumulated by the raster reverse
 // pass, one 64-byte line per record: dL/dmu' (2), dL/dA for the symmetric
 // conic (A00, A01, A11 as full-matrix entries), dL/do, dL/db, dL/dcolour (3).
-// Each line is cleared after it is read, so the accumulator is zero again
-// for the next reverse pass.  Output: dL/dparameter for every parameter of
+// Only the lines the raster pass sent gradient to are read: their records'
+// bits in gradmask (on a dense scene most visible records are occluded and
+// receive none).  Each line read is cleared, and so are the mask bits, so
+// the accumulator is zero again for the next reverse pass.  Output: dL/dparameter for every parameter of
 // Sec. 3.2 Eq. (4) and Sec. 3.3 Eq. (8), added to the caller's buffers, or,
 // in store mode (DBS_FLAG_GRAD_STORE), written over them: every element of
 // every splat is then written, zero for a splat no view sees.  In store mode
@@ -22,7 +24,7 @@
 //
 // Each splat's per-view terms are summed over the views before the single
 // chain to (q, s), and parameters are read and gradients written once.  The
-// per-view terms are computed on packed work lists of the visible records
+// per-view terms are computed on packed work lists of the records with gradient
 // (see below), each added into its splat's accumulators in LDS.  Two kernels
 // with disjoint register needs: the geometric chain (FP64) and the colour
 // chain (Spherical Beta lobes in FP32), which clears the lines.
@@ -45,24 +47,23 @@ __device__ __forceinline__ bool line_is_zero(const float4 a, const float4 b, con
            b.w == 0.f && c.x == 0.f && c.y == 0.f;
 }
 
-// Work lists.  A splat is seen by only some of the views, and a thread that
-// loops over every view for its own splat idles in the views it does not
-// see (a quarter of the lanes were busy).  Instead, each wavefront lists the
-// (splat, view) records of its 64 splats that the views see -- view-major,
-// a window of kItemViews views at a time -- and processes that list 64
-// records at a time, every lane busy.  A record's terms are added into its
+// Work lists.  Only some of a splat's records hold gradient, and a thread
+// that loops over every view for its own splat idles in the others.
+// Instead, each wavefront lists the (splat, view) records of its 64 splats
+// whose gradmask bit is set -- view-major, a window of kItemViews views at a
+// time -- and processes that list 64 records at a time, every lane busy.  A record's terms are added into its
 // splat's accumulators in LDS; a splat appears at most once per view, and
 // the list is view-major, so a splat's terms are added in view order.
 // The per-splat parts (Sigma from q and s before, the chain to q and s after)
 // are done by the splat's own lane.
 constexpr int kPackWaves = 4;
-constexpr int kItemViews = 16;  // divides 64: a window's visibility bits share one word
-static_assert(64 % kItemViews == 0, "item windows must not straddle visibility words");
+constexpr int kItemViews = 16;  // divides 64: a window's mask bits share one word
+static_assert(64 % kItemViews == 0, "item windows must not straddle mask words");
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
 
-// Lists the records (lane, v), v in [v0, v1), of the wavefront's splats that
-// view v sees, view-major; returns the count.  item = lane | v << 6.
+// Lists the records (lane, v), v in [v0, v1), of the wavefront's splats whose
+// bit v is set in vm, view-major; returns the count.  item = lane | v << 6.
 __device__ __forceinline__ int list_items(uint64_t vm, bool live, int v0, int v1, uint16_t *items, int lane)
 {
     int cnt = 0;
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(64 * kPackWaves) void project_bwd_geometry_kernel(S
 
     for (int v0 = 0; v0 < n_views; v0 += kItemViews) {
         const int v1 = v0 + kItemViews < n_views ? v0 + kItemViews : n_views;
-        const uint64_t vm = live ? P.vismask[(int64_t)(v0 >> 6) * n + i] : 0ull;
+        const uint64_t vm = live ? P.gradmask[(int64_t)(v0 >> 6) * n + i] : 0ull;
         const int cnt = list_items(vm, live, v0, v1, s_item[w], lane);
         __syncthreads();
         // each group's accumulator lines are loaded while the previous group computes
@@ -329,6 +330,22 @@ __device__ __forceinline__ float lobe_log2(double d)
     return d < 0.5 ? lo : hi;
 }
 
+// Store mode, a splat with no colour gradient: its colour gradients are zero
+// (the geometry kernel has stored the means' zeros).
+template <int M>
+__device__ __forceinline__ void store_zero_color(const GradPtrs &g, int64_t i)
+{
+    for (int k = 0; k < 3; ++k) g.diffuse[3 * i + k] = 0.0f;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int64_t l = i * M + m;
+        g.lobe_angles[2 * l] = 0.0f;
+        g.lobe_angles[2 * l + 1] = 0.0f;
+        for (int c = 0; c < 3; ++c) g.lobe_colors[3 * l + c] = 0.0f;
+        g.lobe_betas[l] = 0.0f;
+    }
+}
+
 template <int M>
 __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, ProjPtrs P, int32_t n_views,
                                                                 GradPtrs g, int store)
@@ -336,6 +353,14 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
     const int64_t n = sp.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !proj_matches(P, n, n_views)) return;
+    {   // a splat none of whose records has gradient reads no parameters
+        uint64_t anyw = 0;
+        for (int32_t k = 0; k < (n_views + 63) / 64; ++k) anyw |= P.gradmask[(int64_t)k * n + i];
+        if (!anyw) {
+            if (store) store_zero_color<M>(g, i);
+            return;
+        }
+    }
     constexpr int MM = M > 0 ? M : 1;
     const double mu[3] = {sp.means[3 * i], sp.means[3 * i + 1], sp.means[3 * i + 2]};
     double st[MM], ct[MM], sph[MM], cph[MM];
@@ -356,39 +381,18 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
         gcm[m][0] = gcm[m][1] = gcm[m][2] = 0.0f;
     }
     bool any = false;
-    // one view ahead and visible records only, as in the geometry kernel
-    uint64_t vm = P.vismask[i];
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 na = z4, nb = z4, nc = z4;
-    if (vm & 1u) {
-        na = P.sgrad[4 * i];
-        nb = P.sgrad[4 * i + 1];
-        nc = P.sgrad[4 * i + 2];
-    }
-    for (int32_t v = 0; v < n_views; ++v) {
-        float4 *line = P.sgrad + 4 * ((int64_t)v * n + i);
-        const float4 ga = na, gbv = nb, gcv = nc;
-        const bool vis = (vm >> (v & 63)) & 1u;
-        na = nb = nc = z4;
-        if (v + 1 < n_views) {
-            if (((v + 1) & 63) == 0) vm = P.vismask[(int64_t)((v + 1) >> 6) * n + i];
-            if ((vm >> ((v + 1) & 63)) & 1u) {
-                const float4 *nl = line + 4 * n;
-                na = nl[0];
-                nb = nl[1];
-                nc = nl[2];
-            }
-        }
-        if (!vis || line_is_zero(ga, gbv, gcv)) continue;
+    // one record's colour gradient: dL/dcolour of view v from its line (ga, gbv, gcv)
+    auto record = [&](int32_t v, float4 *line, const float4 ga, const float4 gbv, const float4 gcv) {
+        if (line_is_zero(ga, gbv, gcv)) return;
         {
             const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
             line[0] = z; line[1] = z; line[2] = z; line[3] = z;
         }
         const float gcf[3] = {gbv.w, gcv.x, gcv.y};
-        if (gcf[0] == 0.f && gcf[1] == 0.f && gcf[2] == 0.f) continue;
+        if (gcf[0] == 0.f && gcf[1] == 0.f && gcf[2] == 0.f) return;
         any = true;
         for (int c = 0; c < 3; ++c) gc0[c] += gcf[c];
-        if (M == 0) continue;
+        if (M == 0) return;
         ConstViewDesc &V = const_view(P.views, v);
         double vd3[3];
         for (int k = 0; k < 3; ++k)
@@ -421,19 +425,39 @@ __global__ __launch_bounds__(256) void project_bwd_color_kernel(SplatPtrs sp, Pr
         }
         const double vdot = aV[0] * Vd[0] + aV[1] * Vd[1] + aV[2] * Vd[2];
         for (int k = 0; k < 3; ++k) gmu[k] += (float)((aV[k] - Vd[k] * vdot) * ivl);
+    };
+    // Only the records the raster pass sent gradient to, one set mask bit after
+    // another (a lane does as many steps as its splat has such records, not one
+    // per view); the next record's line is loaded while one computes.  This
+    // kernel runs last and clears the mask words and the lines it reads.
+    for (int32_t w0 = 0; w0 < n_views; w0 += 64) {
+        uint64_t *wd = &P.gradmask[(int64_t)(w0 >> 6) * n + i];
+        uint64_t vm = *wd;
+        if (!vm) continue;
+        *wd = 0ull;
+        int32_t v = w0 + __builtin_ctzll(vm);
+        vm &= vm - 1;
+        float4 *line = P.sgrad + 4 * ((int64_t)v * n + i);
+        float4 na = line[0], nb = line[1], nc = line[2];
+        for (;;) {
+            const int32_t cv = v;
+            float4 *cl = line;
+            const float4 ga = na, gbv = nb, gcv = nc;
+            const bool more = vm != 0;
+            if (more) {
+                v = w0 + __builtin_ctzll(vm);
+                vm &= vm - 1;
+                line = P.sgrad + 4 * ((int64_t)v * n + i);
+                na = line[0];
+                nb = line[1];
+                nc = line[2];
+            }
+            record(cv, cl, ga, gbv, gcv);
+            if (!more) break;
+        }
     }
     if (!any) {
-        if (store) {  // the geometry kernel has stored the means' zeros
-            for (int k = 0; k < 3; ++k) g.diffuse[3 * i + k] = 0.0f;
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const int64_t l = i * M + m;
-                g.lobe_angles[2 * l] = 0.0f;
-                g.lobe_angles[2 * l + 1] = 0.0f;
-                for (int c = 0; c < 3; ++c) g.lobe_colors[3 * l + c] = 0.0f;
-                g.lobe_betas[l] = 0.0f;
-            }
-        }
+        if (store) store_zero_color<M>(g, i);
         return;
     }
     // the means always add: the geometry kernel has written its part

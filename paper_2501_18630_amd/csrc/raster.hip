@@ -17,6 +17,8 @@
 //   dL/do = dL/dalpha B,  dL/db = dL/dalpha o B ln(1 - r^2) beta,
 //   dL/dr^2 = -dL/dalpha o beta B / (1 - r^2)  (all zero when alpha is clamped),
 //   dL/dmu' = -2 dL/dr^2 A d,   dL/dA = dL/dr^2 d d^T.
+// Every record that is sent a non-zero sum also gets its bit in gradmask, so
+// that the projection's reverse pass reads only the lines that hold gradient.
 // The per-pixel terms are summed without their per-splat factors (o, beta,
 // A), which are applied once per (tile, splat) before the global atomics.
 // The ten per-(pixel, splat) values are summed over each 16-lane row with a
@@ -56,6 +58,7 @@ struct RasterArgs {
     int32_t *last_index;
     const float *dL_dimage;
     float *sgrad;     // [R][16] screen-space gradient per record
+    uint64_t *gradmask;  // [(V+63)/64][n]: records whose sgrad line was sent gradient
     float t_eps, alpha_max;
     int32_t persistent;
     unsigned long long *atomics;  // counting reverse pass only: global float atomics issued (added to)
@@ -673,6 +676,14 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                     sg[3] *= -obt;
                     sg[4] *= -obt;
                     sg[6] *= obt * kLn2;
+                    bool any = false;
+#pragma unroll
+                    for (int f = 0; f < NG; ++f) any = any || sg[f] != 0.0f;
+                    if (any) {
+                        const int64_t i = (int64_t)s_rec[k] - (int64_t)it.v * a.n;
+                        atomicOr((unsigned long long *)&a.gradmask[(int64_t)(it.v >> 6) * a.n + i],
+                                 1ull << (it.v & 63));
+                    }
                 }
                 __syncthreads();
                 // consecutive lanes take consecutive values of a record: each wave-wide
@@ -931,6 +942,7 @@ hipError_t launch_raster_bwd(ProjPtrs P, BinsPtrs B, int64_t n, int32_t n_views,
     a.last_index = (int32_t *)last_index;
     a.dL_dimage = dL_dimage;
     a.sgrad = sgrad;
+    a.gradmask = P.gradmask;
     a.atomics = (unsigned long long *)atomics;
     return launch(atomics ? e->bwd_count : e->bwd, cfg.tile_w * cfg.tile_h, a, n_tiles, s);
 }
