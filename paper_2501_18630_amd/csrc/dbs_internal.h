@@ -77,8 +77,11 @@ struct alignas(64) RasterRec {
 };
 static_assert(sizeof(RasterRec) == 64, "RasterRec layout");
 
+// Words per view of the visibility bits: whole blocks of 4096 splats.
+__host__ __device__ inline int64_t visbits_stride(int64_t n) { return (n + 4095) / 4096 * 128; }
+
 struct ProjLayout {
-    size_t header, views, rec, bbox, depth, ntiles, gradmask, sgrad, total;
+    size_t header, views, rec, bbox, depth, ntiles, visbits, gradmask, sgrad, total;
 };
 inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     ProjLayout L;
@@ -89,6 +92,7 @@ inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     L.bbox = o;   o = align_up(o + 8 * R);
     L.depth = o;  o = align_up(o + 4 * R);
     L.ntiles = o; o = align_up(o + 4 * R);
+    L.visbits = o; o = align_up(o + 4 * (size_t)n_views * (size_t)visbits_stride(n));
     L.gradmask = o; o = align_up(o + 8 * (size_t)n * (size_t)((n_views + 63) / 64));
     L.sgrad = o;  o = align_up(o + 64 * R);   // screen-space gradient, one 64-byte line per record
     L.total = o;
@@ -143,7 +147,8 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     L.vals_b = o;   o = align_up(o + 4 * R);
     // output offsets of blocks of 4096 records (compaction, pair counts) and
     // the pair counts of their groups of 256 records (pair emission)
-    L.block_sum = o; o = align_up(o + 4 * (size_t)ceil_div((int64_t)R > 0 ? (int64_t)R : 1, 4096));
+    const int64_t nbs = ceil_div((int64_t)R > 0 ? (int64_t)R : 1, 4096), nbc = n_views * ceil_div(n, 4096);
+    L.block_sum = o; o = align_up(o + 4 * (size_t)(nbs > nbc ? nbs : nbc));
     L.group_sum = o; o = align_up(o + 4 * (size_t)ceil_div((int64_t)R > 0 ? (int64_t)R : 1, 256));
     L.pkeys_a = o;  o = align_up(o + 4 * (size_t)cap);
     L.pkeys_b = o;  o = align_up(o + 4 * (size_t)cap);
@@ -194,6 +199,10 @@ struct ProjPtrs {
     RasterRec *rec;
     short4 *bbox;
     uint32_t *depth, *ntiles;
+    // [V][visbits_stride(n)]: bit i % 32 of word i / 32 of row v set when record
+    // (v, i) has ntiles > 0; a row covers whole blocks of 4096 splats (the
+    // padding bits stay zero)
+    uint32_t *visbits;
     // [(V+63)/64][n]: bit v%64 of word v/64 set when the raster reverse pass has
     // sent gradient to record (v, i)'s line of sgrad; cleared with the line
     uint64_t *gradmask;
@@ -209,6 +218,7 @@ inline ProjPtrs proj_ptrs(void *base, int64_t n, int32_t n_views) {
     p.bbox = (short4 *)(b + L.bbox);
     p.depth = (uint32_t *)(b + L.depth);
     p.ntiles = (uint32_t *)(b + L.ntiles);
+    p.visbits = (uint32_t *)(b + L.visbits);
     p.gradmask = (uint64_t *)(b + L.gradmask);
     p.sgrad = (float4 *)(b + L.sgrad);
     return p;

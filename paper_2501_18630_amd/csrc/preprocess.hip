@@ -317,6 +317,12 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
             }
             P.bbox[rec] = bb;
             P.ntiles[rec] = ntiles;
+            {   // the wavefront's 64 visibility bits of this view (i0 is a multiple of 64)
+                const uint64_t vbits = __ballot(ntiles > 0);
+                if (lane == 0)
+                    *reinterpret_cast<uint2 *>(P.visbits + (int64_t)v * visbits_stride(n) + (i0 >> 5)) =
+                        make_uint2((uint32_t)vbits, (uint32_t)(vbits >> 32));
+            }
         }
     }
     vis = wave_sum_u64(vis);

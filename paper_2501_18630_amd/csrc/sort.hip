@@ -78,65 +78,16 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp /*[N
 
 // ---------------------------------------------------------------- scans
 
-// Single-block exclusive scan of partials[0..nb), in place.  With `items`
-// set, only the ceil(*items / per_block) partials of blocks that hold items
-// are scanned (the grid before it was sized for the capacity).
-__global__ __launch_bounds__(1024) void scan_partials_kernel(uint32_t *partials, int64_t nb,
-                                                             const uint32_t *items = nullptr, int per_block = 1)
+// Exclusive scan of row[0..n) in place by one workgroup of NT threads, each
+// taking 16 consecutive entries of a tile of 16 NT (four 16-byte loads and
+// stores; row must start on 16 bytes); returns the total.
+template <int NT>
+__device__ uint32_t scan_in_place(uint32_t *row, int64_t n, uint32_t *s_tmp /*[NT/kWave + 1]*/)
 {
-    if (items) {
-        const int64_t used = ((int64_t)*items + per_block - 1) / per_block;
-        if (used < nb) nb = used;
-    }
-    __shared__ uint32_t s_w[1024 / kWave + 1];
-    __shared__ uint32_t s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    for (int64_t base = 0; base < nb; base += 1024) {
-        const int64_t i = base + threadIdx.x;
-        uint32_t v = i < nb ? partials[i] : 0, x = v;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            uint32_t y = __shfl_up(x, off, kWave);
-            if (lane >= off) x += y;
-        }
-        if (lane == kWave - 1) s_w[w] = x;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t acc = 0;
-            for (int k = 0; k < 1024 / kWave; ++k) {
-                uint32_t c = s_w[k];
-                s_w[k] = acc;
-                acc += c;
-            }
-            s_w[1024 / kWave] = acc;
-        }
-        __syncthreads();
-        if (i < nb) partials[i] = s_carry + s_w[w] + x - v;
-        __syncthreads();
-        if (threadIdx.x == 0) s_carry += s_w[1024 / kWave];
-        __syncthreads();
-    }
-}
-
-// Exclusive scan of each digit's row of the digit-major histogram of a radix
-// pass, over the blocks that hold keys, in place; workgroup d also writes the
-// digit's total.  Row d is contiguous and starts on 16 bytes (the row stride
-// is a multiple of 4); each of kDigitScanThreads threads scans 16 consecutive
-// entries of a tile, moved as four 16-byte loads and stores.
-constexpr int kDigitScanThreads = 1024;
-__global__ __launch_bounds__(kDigitScanThreads) void scan_digits_kernel(uint32_t *hist, int64_t hstride, Count cnt,
-                                                                        uint32_t *totals)
-{
-    __shared__ uint32_t s_tmp[kDigitScanThreads / kWave + 1];
-    const int64_t n = cnt.get();
-    const int64_t nb_used = (n + kSortTile - 1) / kSortTile;
-    uint32_t *row = hist + (int64_t)blockIdx.x * hstride;
     uint32_t carry = 0;
-    for (int64_t base = 0; base < nb_used; base += 16 * kDigitScanThreads) {  // uniform
+    for (int64_t base = 0; base < n; base += 16 * NT) {  // uniform
         const int64_t e0 = base + (int64_t)threadIdx.x * 16;
-        const bool whole = e0 + 16 <= nb_used;
+        const bool whole = e0 + 16 <= n;
         uint32_t v[16], acc = 0;
         if (whole) {
             const uint4 *src = reinterpret_cast<const uint4 *>(row + e0);
@@ -150,12 +101,12 @@ __global__ __launch_bounds__(kDigitScanThreads) void scan_digits_kernel(uint32_t
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] = e0 + k < nb_used ? row[e0 + k] : 0u;
+            for (int k = 0; k < 16; ++k) v[k] = e0 + k < n ? row[e0 + k] : 0u;
         }
 #pragma unroll
         for (int k = 0; k < 16; ++k) acc += v[k];
         uint32_t total;
-        uint32_t pre = carry + block_exclusive_scan<kDigitScanThreads>(acc, s_tmp, &total);
+        uint32_t pre = carry + block_exclusive_scan<NT>(acc, s_tmp, &total);
         uint32_t o[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -169,11 +120,39 @@ __global__ __launch_bounds__(kDigitScanThreads) void scan_digits_kernel(uint32_t
         } else {
 #pragma unroll
             for (int k = 0; k < 16; ++k)
-                if (e0 + k < nb_used) row[e0 + k] = o[k];
+                if (e0 + k < n) row[e0 + k] = o[k];
         }
         carry += total;
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    return carry;
+}
+
+// Single-block exclusive scan of partials[0..nb), in place.  With `items`
+// set, only the ceil(*items / per_block) partials of blocks that hold items
+// are scanned (the grid before it was sized for the capacity).
+__global__ __launch_bounds__(1024) void scan_partials_kernel(uint32_t *partials, int64_t nb,
+                                                             const uint32_t *items = nullptr, int per_block = 1)
+{
+    __shared__ uint32_t s_tmp[1024 / kWave + 1];
+    if (items) {
+        const int64_t used = ((int64_t)*items + per_block - 1) / per_block;
+        if (used < nb) nb = used;
+    }
+    scan_in_place<1024>(partials, nb, s_tmp);
+}
+
+// Exclusive scan of each digit's row of the digit-major histogram of a radix
+// pass, over the blocks that hold keys, in place; workgroup d also writes the
+// digit's total.  Rows start on 16 bytes (the row stride is a multiple of 4).
+constexpr int kDigitScanThreads = 1024;
+__global__ __launch_bounds__(kDigitScanThreads) void scan_digits_kernel(uint32_t *hist, int64_t hstride, Count cnt,
+                                                                        uint32_t *totals)
+{
+    __shared__ uint32_t s_tmp[kDigitScanThreads / kWave + 1];
+    const int64_t n = cnt.get();
+    const int64_t nb_used = (n + kSortTile - 1) / kSortTile;
+    const uint32_t total = scan_in_place<kDigitScanThreads>(hist + (int64_t)blockIdx.x * hstride, nb_used, s_tmp);
+    if (threadIdx.x == 0) totals[blockIdx.x] = total;
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -450,77 +429,77 @@ __global__ void finalize_counts_kernel(const ProjHeader *ph, BinsHeader *bh, int
     if (overflow_out) *overflow_out = ovf;
 }
 
-// Compaction of the visible records (tile count > 0) in record order: each
-// block takes 4096 consecutive records (16 consecutive ones per thread, read
-// as four 16-byte loads); a first pass counts each block's visible records,
-// their exclusive scan gives each block its output offset, and a second pass
-// ranks the visible records inside the block and writes the (depth key,
-// record) pairs contiguously through LDS.
+// Compaction of the visible records (tile count > 0) in record order, from
+// the visibility bits the preprocess writes: each block takes 4096
+// consecutive splats of one view (16 per thread, half a bit word); a first
+// pass counts each block's visible records (one wavefront per block, a
+// popcount of 128 words), their exclusive scan gives each block its output
+// offset, and a second pass ranks the visible records inside the block and
+// writes the (depth key, record) pairs contiguously through LDS.  Blocks go
+// view by view, so the output is in record order.
 constexpr int kCompactItems = 16;
 constexpr int kCompactTile = kSortThreads * kCompactItems;
 
-__device__ __forceinline__ void load_counts16(const uint32_t *ntiles, int64_t e0, int64_t n, uint32_t nt[16])
+__global__ __launch_bounds__(kSortThreads) void count_visible_kernel(const BinsHeader *bh, const uint32_t *visbits,
+                                                                     int64_t vstride, int64_t nbv, int64_t nbc,
+                                                                     uint32_t *counts)
 {
-    if (e0 + kCompactItems <= n) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(ntiles + e0);
-#pragma unroll
-        for (int q = 0; q < kCompactItems / 4; ++q) {
-            const uint4 u = src[q];
-            nt[4 * q] = u.x;
-            nt[4 * q + 1] = u.y;
-            nt[4 * q + 2] = u.z;
-            nt[4 * q + 3] = u.w;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < kCompactItems; ++q) nt[q] = e0 + q < n ? ntiles[e0 + q] : 0u;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t b = (int64_t)blockIdx.x * (kSortThreads / kWave) + threadIdx.x / kWave;
+    if (b >= nbc) return;  // uniform per wavefront
+    uint32_t c = 0;
+    if (bh->n_rec) {  // 0 when the buffers do not match
+        const int64_t v = b / nbv, j = b - v * nbv;
+        const uint2 w2 = *reinterpret_cast<const uint2 *>(visbits + v * vstride + j * 128 + 2 * lane);
+        c = (uint32_t)(__popc(w2.x) + __popc(w2.y));
     }
-}
-
-__global__ __launch_bounds__(kSortThreads) void count_visible_kernel(const BinsHeader *bh, const uint32_t *ntiles,
-                                                                     uint32_t *partials)
-{
-    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
-    const int64_t n = bh->n_rec;  // 0 when the buffers do not match
-    const int64_t e0 = (int64_t)blockIdx.x * kCompactTile + (int64_t)threadIdx.x * kCompactItems;
-    uint32_t nt[kCompactItems];
-    load_counts16(ntiles, e0, n, nt);
-    uint32_t cnt = 0;
 #pragma unroll
-    for (int q = 0; q < kCompactItems; ++q) cnt += nt[q] > 0u;
-    uint32_t total;
-    block_exclusive_scan(cnt, s_tmp, &total);
-    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+    if (lane == 0) counts[b] = c;
 }
 
-__global__ __launch_bounds__(kSortThreads) void compact_visible_kernel(const BinsHeader *bh, const uint32_t *ntiles,
+__global__ __launch_bounds__(kSortThreads) void compact_visible_kernel(const BinsHeader *bh, const uint32_t *visbits,
+                                                                       int64_t vstride, int64_t nbv, int64_t n,
                                                                        const uint32_t *depth,
                                                                        const uint32_t *offsets, uint32_t *keys,
                                                                        uint32_t *vals)
 {
     __shared__ uint2 s_out[kCompactTile];
     __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
-    const int64_t n = bh->n_rec;
-    const int64_t base = (int64_t)blockIdx.x * kCompactTile;
-    if (base >= n) return;  // uniform
+    if (bh->n_rec == 0) return;  // uniform: the buffers do not match
     const int t = threadIdx.x;
-    const int64_t e0 = base + (int64_t)t * kCompactItems;
-    uint32_t nt[kCompactItems];
-    load_counts16(ntiles, e0, n, nt);
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int q = 0; q < kCompactItems; ++q) cnt += nt[q] > 0u;
+    const int64_t v = (int64_t)blockIdx.x / nbv, j = (int64_t)blockIdx.x - v * nbv;
+    const uint32_t bits =
+        (visbits[v * vstride + j * 128 + (t >> 1)] >> ((t & 1) * kCompactItems)) & ((1u << kCompactItems) - 1u);
     uint32_t total;
-    uint32_t r = block_exclusive_scan(cnt, s_tmp, &total);
+    uint32_t r = block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
+    const int64_t i_lo = j * kCompactTile + (int64_t)t * kCompactItems, rec0 = v * n + i_lo;
+    uint32_t dk[kCompactItems];
+    if (bits) {  // padding bits past n are zero
+        if ((n & 3) == 0 && i_lo + kCompactItems <= n) {  // 16-byte aligned, all in range: four vector loads
+            const uint4 *src = reinterpret_cast<const uint4 *>(depth + rec0);
 #pragma unroll
-    for (int q = 0; q < kCompactItems; ++q)
-        if (nt[q] > 0u) s_out[r++] = make_uint2(depth[e0 + q], (uint32_t)(e0 + q));
+            for (int q = 0; q < kCompactItems / 4; ++q) {
+                const uint4 u = src[q];
+                dk[4 * q] = u.x;
+                dk[4 * q + 1] = u.y;
+                dk[4 * q + 2] = u.z;
+                dk[4 * q + 3] = u.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kCompactItems; ++k) dk[k] = ((bits >> k) & 1u) ? depth[rec0 + k] : 0u;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k)
+        if ((bits >> k) & 1u) s_out[r++] = make_uint2(dk[k], (uint32_t)(rec0 + k));
     __syncthreads();
     const uint32_t out = offsets[blockIdx.x];
-    for (uint32_t j = t; j < total; j += kSortThreads) {
-        const uint2 kv = s_out[j];
-        keys[out + j] = kv.x;
-        vals[out + j] = kv.y;
+    for (uint32_t q = t; q < total; q += kSortThreads) {
+        const uint2 kv = s_out[q];
+        keys[out + q] = kv.x;
+        vals[out + q] = kv.y;
     }
 }
 
@@ -751,11 +730,12 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
 
     // 1. compact visible records, then sort them by depth bits
     if (R > 0) {
-        const int64_t nb = ceil_div(R, kCompactTile);
-        count_visible_kernel<<<(unsigned)nb, kSortThreads, 0, s>>>(B.hdr, P.ntiles, block_sum);
-        scan_partials_kernel<<<1, 1024, 0, s>>>(block_sum, nb, &B.hdr->n_rec, kCompactTile);
-        compact_visible_kernel<<<(unsigned)nb, kSortThreads, 0, s>>>(B.hdr, P.ntiles, P.depth, block_sum, keys_a,
-                                                                     vals_a);
+        const int64_t nbv = ceil_div(n, kCompactTile), nbc = n_views * nbv, vstride = visbits_stride(n);
+        count_visible_kernel<<<(unsigned)ceil_div(nbc, kSortThreads / kWave), kSortThreads, 0, s>>>(
+            B.hdr, P.visbits, vstride, nbv, nbc, block_sum);
+        scan_partials_kernel<<<1, 1024, 0, s>>>(block_sum, nbc);
+        compact_visible_kernel<<<(unsigned)nbc, kSortThreads, 0, s>>>(B.hdr, P.visbits, vstride, nbv, n, P.depth,
+                                                                      block_sum, keys_a, vals_a);
     }
     const Count vis_cnt{&B.hdr->n_vis, R};
     bool depth_in_b = false;
