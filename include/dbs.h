@@ -401,6 +401,21 @@ dbs_status dbs_raster_bwd_count(const void *projected, const void *bins, const d
 dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views, void **record, void **bbox,
                                 void **depth, void **ntiles, void **counts);
 
+/* Device pointers into `projected` to the state the calls keep between them
+ * (inspection and tests):
+ *   visbits  [n_views][S] uint32, S = 128 ceil(n / 4096): bit i % 32 of word
+ *            i / 32 of row v is ntiles > 0 of record (v, i) (written by the
+ *            preprocess; bits past n are zero)
+ *   gradmask [ceil(n_views / 64)][n] uint64: bit v % 64 of word (v / 64, i)
+ *            marks record (v, i) as holding gradient in its accumulator line
+ *            (set by dbs_raster_bwd, cleared by dbs_project_bwd)
+ *   sgrad    [R] 64-byte accumulator line per record: float dL/dmu' (2),
+ *            dL/dA00, dL/dA01, dL/dA11, dL/do, dL/db, dL/dcolour (3), 6 unused
+ * Between a dbs_project_bwd and the next dbs_raster_bwd, gradmask and sgrad
+ * are all zero.  Any output pointer may be NULL. */
+dbs_status dbs_projected_state(void *projected, int64_t n, int32_t n_views, void **visbits, void **gradmask,
+                               void **sgrad);
+
 /* Device pointers into `bins`:
  *   pair_rec   [pair_capacity] uint32 record r = v n + i per pair, sorted
  *   tile_range [n_tiles] uint32x2 (start, end) into pair_rec per global tile

@@ -32,7 +32,7 @@ EXPORTS = ("dbs_default_cfg", "dbs_projected_bytes", "dbs_bins_bytes", "dbs_work
            "dbs_photometric_loss", "dbs_regularizer", "dbs_mcmc_workspace_bytes", "dbs_mcmc_relocate",
            "dbs_mcmc_noise",
            "dbs_raster_bwd", "dbs_raster_bwd_count", "dbs_project_bwd", "dbs_render_stats",
-           "dbs_projected_layout", "dbs_bins_layout", "dbs_status_string", "dbs_version")
+           "dbs_projected_layout", "dbs_projected_state", "dbs_bins_layout", "dbs_status_string", "dbs_version")
 
 
 class DbsError(RuntimeError):
@@ -91,11 +91,12 @@ def _declare(lib):
     lib.dbs_mcmc_relocate.argtypes = [P, C.c_float, P, P, SZ, P, P]
     lib.dbs_mcmc_noise.argtypes = [P, P, C.c_float, C.c_float, C.c_float, P]
     lib.dbs_projected_layout.argtypes = [P, I64, I32] + [C.POINTER(C.c_void_p)] * 5
+    lib.dbs_projected_state.argtypes = [P, I64, I32] + [C.POINTER(C.c_void_p)] * 3
     lib.dbs_bins_layout.argtypes = [P, I64, P, I32, P] + [C.POINTER(C.c_void_p)] * 3 + [C.POINTER(C.c_int64)]
     for f in ("dbs_preprocess", "dbs_preprocess_gaussian_sh", "dbs_bin_sort", "dbs_bin_sort_noalloc", "dbs_render_fwd", "dbs_render_bwd", "dbs_l1_loss",
               "dbs_photometric_loss", "dbs_regularizer", "dbs_mcmc_workspace_bytes", "dbs_mcmc_relocate",
            "dbs_mcmc_noise", "dbs_raster_bwd", "dbs_raster_bwd_count", "dbs_project_bwd", "dbs_render_stats",
-              "dbs_projected_layout", "dbs_bins_layout"):
+              "dbs_projected_layout", "dbs_projected_state", "dbs_bins_layout"):
         getattr(lib, f).restype = C.c_int
     lib.dbs_status_string.argtypes = [C.c_int]
     lib.dbs_status_string.restype = C.c_char_p

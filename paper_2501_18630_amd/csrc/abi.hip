@@ -405,6 +405,17 @@ dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views, voi
     return DBS_OK;
 }
 
+dbs_status dbs_projected_state(void *projected, int64_t n, int32_t n_views, void **visbits, void **gradmask,
+                               void **sgrad)
+{
+    if (!projected || n < 0 || n_views < 1 || n_views > DBS_MAX_VIEWS) return DBS_ERR_INVALID_ARGUMENT;
+    ProjPtrs P = proj_ptrs(projected, n, n_views);
+    if (visbits) *visbits = P.visbits;
+    if (gradmask) *gradmask = P.gradmask;
+    if (sgrad) *sgrad = P.sgrad;
+    return DBS_OK;
+}
+
 dbs_status dbs_bins_layout(void *bins, int64_t pair_capacity, const dbs_camera *cams, int32_t n_views,
                            const dbs_raster_cfg *cfg, void **pair_rec, void **tile_range, void **tile_order,
                            int64_t *n_tiles)

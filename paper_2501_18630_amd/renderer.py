@@ -286,6 +286,23 @@ class Rasterizer:
                     ntiles=sl(ptrs[3], 4 * R).view(torch.int32).view(R),
                     counts=sl(ptrs[4], 16).view(torch.int64).view(2))
 
+    def state(self) -> dict:
+        """Visibility bits [V, S] (int32 words), gradient mask [ceil(V/64), n]
+        (int64 words) and accumulator lines [R, 16] (float32) in `projected`."""
+        ptrs = [C.c_void_p() for _ in range(3)]
+        check("dbs_projected_state", self.lib.dbs_projected_state(
+            C.c_void_p(self.projected.data_ptr()), self.n, self.V, *[C.byref(p) for p in ptrs]))
+        base = self.projected.data_ptr()
+        R, S, W = self.n * self.V, (self.n + 4095) // 4096 * 128, (self.V + 63) // 64
+
+        def sl(p, nbytes):
+            off = p.value - base
+            return self.projected[off:off + nbytes]
+
+        return dict(visbits=sl(ptrs[0], 4 * self.V * S).view(torch.int32).view(self.V, S),
+                    gradmask=sl(ptrs[1], 8 * W * self.n).view(torch.int64).view(W, self.n),
+                    sgrad=sl(ptrs[2], 64 * R).view(torch.float32).view(R, 16))
+
     def bins_arrays(self) -> dict:
         ptrs = [C.c_void_p() for _ in range(3)]
         nt = C.c_int64()
