@@ -202,24 +202,27 @@ struct LanePixel {
     }
 };
 
-// min over p in [x0,x1] x [y0,y1] of (p - c)^T A (p - c), A positive definite
+// min over p in [x0,x1] x [y0,y1] of (p - c)^T A (p - c), A positive definite.
+// 0 when c lies in the rectangle.  Otherwise the minimum lies on an edge that
+// faces c: on a vertical edge the minimiser over y has dq/dx = 2 dx det A / A11,
+// which points into the rectangle (q falls inwards) unless c is beyond that
+// edge, and likewise for horizontal edges.  So only the vertical edge on c's
+// side (when c is outside the x range) and the horizontal edge on c's side
+// (outside the y range) are evaluated, each at its minimiser clamped to the
+// edge, which also covers the corners.
 __device__ __forceinline__ float rect_min_r2(float cx, float cy, float a00, float a01, float a11, float x0,
                                              float x1, float y0, float y1)
 {
     const float dx0 = x0 - cx, dx1 = x1 - cx, dy0 = y0 - cy, dy1 = y1 - cy;
-    if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return 0.0f;
+    const bool inx = dx0 <= 0.0f && dx1 >= 0.0f, iny = dy0 <= 0.0f && dy1 >= 0.0f;
     const float r00 = __builtin_amdgcn_rcpf(a00), r11 = __builtin_amdgcn_rcpf(a11);
-    float best = 3.0e38f;
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const float dx = e ? dx1 : dx0;
-        const float dy = fminf(fmaxf(-a01 * dx * r11, dy0), dy1);
-        best = fminf(best, a00 * dx * dx + 2.0f * a01 * dx * dy + a11 * dy * dy);
-        const float ey = e ? dy1 : dy0;
-        const float ex = fminf(fmaxf(-a01 * ey * r00, dx0), dx1);
-        best = fminf(best, a00 * ex * ex + 2.0f * a01 * ex * ey + a11 * ey * ey);
-    }
-    return best;
+    const float dx = dx0 > 0.0f ? dx0 : dx1;  // the facing vertical edge
+    const float dy = fminf(fmaxf(-a01 * dx * r11, dy0), dy1);
+    const float qv = a00 * dx * dx + 2.0f * a01 * dx * dy + a11 * dy * dy;
+    const float ey = dy0 > 0.0f ? dy0 : dy1;  // the facing horizontal edge
+    const float ex = fminf(fmaxf(-a01 * ey * r00, dx0), dx1);
+    const float qh = a00 * ex * ex + 2.0f * a01 * ex * ey + a11 * ey * ey;
+    return inx ? (iny ? 0.0f : qh) : (iny ? qv : fminf(qv, qh));
 }
 
 // Culling threshold for the FP32 minimum of r^2 over a rectangle.  Rounding
