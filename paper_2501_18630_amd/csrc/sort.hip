@@ -21,6 +21,7 @@
 // are read from device memory, so the whole pipeline runs without a host
 // round trip and can be captured in a graph.
 #include <mutex>
+#include <type_traits>
 
 #include "dbs_internal.h"
 
@@ -158,17 +159,23 @@ __global__ __launch_bounds__(kDigitScanThreads) void scan_digits_kernel(uint32_t
 // ---------------------------------------------------------------- radix sort
 
 // Digit match across the wave: mask of valid lanes holding digit d (RB bits).
+// Per bit: m = the bit sign-extended (0 or all ones), its ballot B, and each
+// half of the mask keeps the lanes whose bit agrees, mask & ~(B ^ m) — one
+// three-input bitwise instruction per half, four VALU per bit in all.
 template <int RB>
 __device__ inline uint64_t match_digit(uint32_t d, bool valid)
 {
-    uint64_t peers = __ballot(valid);
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
+        uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+        asm volatile("" : "+v"(m));  // keeps the ballot's compare on m (not a second shift of d)
+        const uint64_t bal = __ballot(m != 0u);
+        lo &= ~((uint32_t)bal ^ m);
+        hi &= ~((uint32_t)(bal >> 32) ^ m);
     }
-    return peers;
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Block b sorts elements [b * kSortTile, (b + 1) * kSortTile); inside it wave w
@@ -216,18 +223,24 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
     const int64_t base = chunk * kSortTile;
     for (int i = t; i < ROWS * STRIDE; i += kSortThreads) s_cnt[i] = 0;
     __syncthreads();
-    if (base < n) {
+    // compiled twice: for a full chunk (all but the last) without bounds tests
+    auto count_chunk = [&](auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
         uint32_t d[kSortItems];
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before any counting
             const int64_t e = sort_elem(base, w, k, lane);
-            d[k] = e < n ? (keys[e] >> shift) & dmask : RADIX;
+            d[k] = FULL || e < n ? (keys[e] >> shift) & dmask : RADIX;
         }
         uint32_t *row = s_cnt + (w * UC + (lane & (UC - 1))) * STRIDE;
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k)
-            if (d[k] < RADIX) atomicAdd(&row[d[k]], 1u);
-    }
+            if (FULL || d[k] < RADIX) atomicAdd(&row[d[k]], 1u);
+    };
+    if (base + kSortTile <= n)
+        count_chunk(std::integral_constant<bool, true>{});
+    else if (base < n)
+        count_chunk(std::integral_constant<bool, false>{});
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
@@ -260,7 +273,6 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
     __shared__ uint32_t s_wh[NW][RADIX];   // per-wave digit counts, then per-wave offsets
-    __shared__ uint32_t s_start[RADIX];
     __shared__ uint32_t s_goff[RADIX];
     __shared__ uint32_t s_tmp[NW + 1];
     const uint32_t dmask = (1u << width) - 1u;
@@ -290,63 +302,76 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     }
     __syncthreads();
 
-    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
-    const uint64_t lt = lanemask_lt();
+    // Loads, ranking and the scatter into LDS, compiled twice: for a chunk
+    // that is full (all but the last), without the per-item bounds tests.
+    const bool full = base + kSortTile <= n;  // uniform across the block
+    auto sort_chunk = [&](auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+        const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
-        const int64_t e = sort_elem(base, w, k, lane);
-        key[k] = e < n ? keys_in[e] : 0u;
-        val[k] = e < n ? vals_in[e] : 0u;
-    }
-    // rank inside the wave: earlier items of this wave, then lower lanes of this item
-#pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
-        const bool valid = sort_elem(base, w, k, lane) < n;
-        const uint32_t d = (key[k] >> shift) & dmask;
-        const uint64_t peers = match_digit<RB>(d, valid);
-        const uint32_t before = s_wh[w][d];
-        if (valid && (peers & lt) == 0) s_wh[w][d] = before + (uint32_t)__popcll(peers);
-        rank[k] = before + (uint32_t)__popcll(peers & lt);
-    }
-    __syncthreads();
-    {   // thread t owns digits t * DPT .. t * DPT + DPT - 1: offsets of the waves, then of the digits
-        uint32_t tot[DPT], sum = 0;
-#pragma unroll
-        for (int q = 0; q < DPT; ++q) {
-            const int dd = t * DPT + q;
-            uint32_t run = 0;
-#pragma unroll
-            for (int ww = 0; ww < NW; ++ww) {
-                const uint32_t c = s_wh[ww][dd];
-                s_wh[ww][dd] = run;
-                run += c;
-            }
-            tot[q] = run;
-            sum += run;
+        for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
+            const int64_t e = sort_elem(base, w, k, lane);
+            key[k] = FULL || e < n ? keys_in[e] : 0u;
+            val[k] = FULL || e < n ? vals_in[e] : 0u;
         }
-        uint32_t st = block_exclusive_scan(sum, s_tmp, nullptr);
+        // rank inside the wave: earlier items of this wave, then lower lanes of this item
 #pragma unroll
-        for (int q = 0; q < DPT; ++q) {
-            s_start[t * DPT + q] = st;
-            st += tot[q];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
-        if (sort_elem(base, w, k, lane) < n) {
+        for (int k = 0; k < kSortItems; ++k) {
+            const bool valid = FULL || sort_elem(base, w, k, lane) < n;
             const uint32_t d = (key[k] >> shift) & dmask;
-            const uint32_t pos = s_start[d] + s_wh[w][d] + rank[k];
-            s_keys[pos] = key[k];
-            s_vals[pos] = val[k];
+            const uint64_t peers = match_digit<RB>(d, valid);
+            const uint32_t before = s_wh[w][d];
+            if (valid && (peers & lt) == 0) s_wh[w][d] = before + (uint32_t)__popcll(peers);
+            rank[k] = before + (uint32_t)__popcll(peers & lt);
         }
-    }
+        __syncthreads();
+        {   // thread t owns digits t * DPT .. t * DPT + DPT - 1: s_wh[w][d] becomes
+            // the LDS position of wave w's first item of digit d, s_goff[d] the
+            // output offset minus digit d's first LDS position
+            uint32_t c[DPT][NW], tot[DPT], sum = 0;
+#pragma unroll
+            for (int q = 0; q < DPT; ++q) {
+                tot[q] = 0;
+#pragma unroll
+                for (int ww = 0; ww < NW; ++ww) {
+                    c[q][ww] = s_wh[ww][t * DPT + q];
+                    tot[q] += c[q][ww];
+                }
+                sum += tot[q];
+            }
+            uint32_t st = block_exclusive_scan(sum, s_tmp, nullptr);
+#pragma unroll
+            for (int q = 0; q < DPT; ++q) {
+                const int dd = t * DPT + q;
+                s_goff[dd] -= st;
+#pragma unroll
+                for (int ww = 0; ww < NW; ++ww) {
+                    s_wh[ww][dd] = st;
+                    st += c[q][ww];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            if (FULL || sort_elem(base, w, k, lane) < n) {
+                const uint32_t pos = s_wh[w][(key[k] >> shift) & dmask] + rank[k];
+                s_keys[pos] = key[k];
+                s_vals[pos] = val[k];
+            }
+        }
+    };
+    if (full)
+        sort_chunk(std::integral_constant<bool, true>{});
+    else
+        sort_chunk(std::integral_constant<bool, false>{});
     __syncthreads();
     const int64_t cnt_blk = n - base < kSortTile ? n - base : kSortTile;
     for (int j = t; j < cnt_blk; j += kSortThreads) {
         const uint32_t kk = s_keys[j];
         const uint32_t d = (kk >> shift) & dmask;
-        const uint32_t o = s_goff[d] + (uint32_t)j - s_start[d];
+        const uint32_t o = s_goff[d] + (uint32_t)j;
         const uint32_t vv = s_vals[j];
         if (!last) keys_out[o] = kk;
         vals_out[o] = vv;
