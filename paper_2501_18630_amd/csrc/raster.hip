@@ -404,6 +404,12 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
     const LanePixel<TW, TH> P(w, lane);
     const double fpx = (double)P.lx + 0.5, fpy = (double)P.ly + 0.5;
     const uint8_t *my_row = &s_rows[w][P.row * BATCH];
+    // A row's entries past its count are read too (and masked): every entry
+    // ever read is then a slot index below BATCH.
+    for (int i = lane; i < 4 * BATCH; i += kWave) s_rows[w][i] = 0;
+    float amax = a.alpha_max;
+    asm volatile("" : "+v"(amax));  // held in a VGPR: the clamp's select then needs no copy per step
+    const float teps = a.t_eps;
 
     for (int iter = 0;; ++iter) {
         if (!fetch_item<TW, TH>(a, &a.queue[0], &s_item, iter)) break;
@@ -411,28 +417,34 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
         const ViewDesc &V = a.views[it.v];
         const int px = it.ox + P.lx, py = it.oy + P.ly;
         const bool inside = px < V.width && py < V.height;
-        bool done = !inside;
-        float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+        // a pixel has stopped once T < t_eps (t_eps >= 0): one outside the view
+        // starts stopped at T = -1, and T only changes while a pixel runs
+        float T = inside ? 1.0f : -1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
         int32_t last = -1;
 
         for (uint32_t start = it.start; start < it.end; start += BATCH) {
-            if (__syncthreads_count(!done) == 0) break;
+            if (__syncthreads_count(!(T < teps)) == 0) break;
             const int nb = (int)min((uint32_t)BATCH, it.end - start);
             stage<TW, TH, true>(a, start, nb, (double)it.ox, (double)it.oy, S, tid);
             __syncthreads();
             // rows whose pixels have all stopped take no entries
-            const uint64_t live = __ballot(!done);
+            const uint64_t live = __ballot(!(T < teps));
             int32_t lim[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) lim[r] = ((live >> (16 * r)) & 0xffffull) ? INT32_MAX : -1;
             const int cnt_b = live ? build_list(s_col, nb, w, s_blist[w], lane) : 0;
             int cnt[4];
             build_rows<BATCH, 0>(S, s_blist[w], cnt_b, P.bx, P.by, (int64_t)start, lim, s_rows[w], cnt, lane);
-            const int my_cnt = pick4(cnt, P.row), steps = max4(cnt);
+            // wave-uniform step bound (a scalar loop counter); the row's list
+            // address is kept in one register (one add per step)
+            const int my_cnt = pick4(cnt, P.row), steps = __builtin_amdgcn_readfirstlane(max4(cnt));
+            int rbase = (w * 4 + P.row) * BATCH;  // my_row, as an index into s_rows
+            asm volatile("" : "+v"(rbase));
             for (int t = 0; t < steps; ++t) {
-                const bool act = t < my_cnt && !done;
-                if (!__ballot(act)) break;
-                const int k = act ? my_row[t] : 0;
+                const bool on = t < my_cnt, running = !(T < teps), act = on && running;
+                // two ballots of plain compares, combined on the scalar unit
+                if (!(__ballot(on) & __ballot(running))) break;
+                const int k = (&s_rows[0][0])[rbase + t];
                 const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
                 const double r2 = eval_r2(fpx - c.x, fpy - c.y, aa.x, aa.y, bb.x);
                 if (act && r2 < 1.0) {
@@ -441,7 +453,7 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                     const float B = GAUSS ? __builtin_amdgcn_exp2f(-6.4921276840003350f * (float)r2)
                                           : eval_kernel((float)(1.0 - r2), ob.y, &lg);
                     bool clamped;
-                    const float alpha = clamp_alpha(__fmul_rn(ob.x, B), a.alpha_max, &clamped);
+                    const float alpha = clamp_alpha(__fmul_rn(ob.x, B), amax, &clamped);
                     const float wgt = alpha * T;
                     const float4 cc = s_col[k];
                     C0 = __fmaf_rn(cc.x, wgt, C0);
@@ -449,7 +461,6 @@ __global__ __launch_bounds__(TW *TH) void raster_fwd_kernel(RasterArgs a)
                     C2 = __fmaf_rn(cc.z, wgt, C2);
                     T = __fmul_rn(T, __fsub_rn(1.0f, alpha));
                     last = (int32_t)(start + (uint32_t)k);
-                    done = T < a.t_eps;
                 }
             }
         }
@@ -510,6 +521,8 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
     // keeps taking valid entries (and contributes nothing) while the other
     // rows of its wavefront step on: the step loop needs no per-lane bounds.
     constexpr int PAD = BATCH + 4, RS = PAD + BATCH;
+    float amax = a.alpha_max;
+    asm volatile("" : "+v"(amax));  // held in a VGPR: the clamp's select then needs no copy per step
     __shared__ double2 s_c[BATCH + 1], s_a[BATCH + 1], s_b[BATCH + 1];
     __shared__ float4 s_col[BATCH + 1];
     __shared__ uint32_t s_rec[BATCH];
@@ -584,7 +597,8 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                 const int nbw = kmax64 < (int64_t)(nb - 1) ? (int)kmax64 + 1 : nb;
                 // this pixel's last contributor as a slot of the batch (-1: none in it)
                 const int64_t lk64 = (int64_t)last - lo;
-                const int last_k = lk64 < 0 ? -1 : (lk64 > (int64_t)BATCH ? BATCH : (int)lk64);
+                int last_k = lk64 < 0 ? -1 : (lk64 > (int64_t)BATCH ? BATCH : (int)lk64);
+                asm volatile("" : "+v"(last_k));  // one compare per step for k <= last_k
                 const int cnt_b = nbw > 0 ? build_list(s_col, nbw, w, s_blist[w], lane) : 0;
                 int cnt[4];
                 build_rows<RS, PAD>(S, s_blist[w], cnt_b, P.bx, P.by, lo, row_last, s_rows[w], cnt, lane);
@@ -597,17 +611,21 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                 for (int step = 0; step < steps; ++step) {
                     const int t = my_cnt - 1 - step;
                     const int k = kl_next;
+                    __builtin_assume(k >= 0 && k <= BATCH);  // list entries are bytes
                     kl_next = my_row[t - 1];
                     const bool owner = fld >= 0;
                     float *dst = &s_g[w][k][owner ? fld : 0];
                     // read early: the slot's running sum, added to at the end of the step
                     const float prev = *dst;
                     const uint32_t share = __builtin_amdgcn_readfirstlane(s_share[w][step]);
-                    const double2 c = s_c[k], aa = s_a[k], bb = s_b[k];
+                    const double2 c = s_c[k], aa = s_a[k];
+                    double2 bb = s_b[k];
+                    asm volatile("" : "+v"(bb.y));  // one 16-byte read of the slot's third pair
                     const double dxd = fpx - c.x, dyd = fpy - c.y;
                     const double r2 = eval_r2(dxd, dyd, aa.x, aa.y, bb.x);
-                    const bool contrib = k <= last_k && r2 < 1.0;
-                    if (!__ballot(contrib)) continue;
+                    const bool live = k <= last_k, in = r2 < 1.0, contrib = live && in;
+                    // two ballots of plain compares, combined on the scalar unit
+                    if (!(__ballot(live) & __ballot(in))) continue;
                     // Branch-free from here: a lane that does not take part uses
                     // r^2 = 0 (finite logs) and alpha = 0 (T, S unchanged), and
                     // its terms are multiplied by zero.
@@ -617,7 +635,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(TW * TH 
                     const float B = eval_kernel(omr, ob.y, &lg);
                     const float araw = __fmul_rn(ob.x, B);
                     bool clamped;
-                    const float alpha_c = clamp_alpha(araw, a.alpha_max, &clamped);
+                    const float alpha_c = clamp_alpha(araw, amax, &clamped);
                     const float alpha = contrib ? alpha_c : 0.0f;
                     const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
                     const float Ti = T * inv;
