@@ -139,16 +139,19 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     int64_t maxn = (int64_t)R;
     if (cap > maxn) maxn = cap;
     if (n_tiles > maxn) maxn = n_tiles;
+    // the depth sort's first pass takes one chunk per 4096 splats of a view
+    const int64_t nbc = (int64_t)n_views * ceil_div(n, kSortTile);
     L.hist_blocks = ceil_div(maxn > 0 ? maxn : 1, kSortTile);
+    if (nbc > L.hist_blocks) L.hist_blocks = nbc;
     size_t hist_n = (size_t)hist_stride(L.hist_blocks) * kMaxRadix;
     L.keys_a = o;   o = align_up(o + 4 * R);
     L.vals_a = o;   o = align_up(o + 4 * R);
     L.keys_b = o;   o = align_up(o + 4 * R);
     L.vals_b = o;   o = align_up(o + 4 * R);
-    // output offsets of blocks of 4096 records (compaction, pair counts) and
-    // the pair counts of their groups of 256 records (pair emission)
-    const int64_t nbs = ceil_div((int64_t)R > 0 ? (int64_t)R : 1, 4096), nbc = n_views * ceil_div(n, 4096);
-    L.block_sum = o; o = align_up(o + 4 * (size_t)(nbs > nbc ? nbs : nbc));
+    // output offsets of blocks of 4096 records (pair counts) and the pair
+    // counts of their groups of 256 records (pair emission)
+    const int64_t nbs = ceil_div((int64_t)R > 0 ? (int64_t)R : 1, 4096);
+    L.block_sum = o; o = align_up(o + 4 * (size_t)nbs);
     L.group_sum = o; o = align_up(o + 4 * (size_t)ceil_div((int64_t)R > 0 ? (int64_t)R : 1, 256));
     L.pkeys_a = o;  o = align_up(o + 4 * (size_t)cap);
     L.pkeys_b = o;  o = align_up(o + 4 * (size_t)cap);

@@ -205,9 +205,52 @@ __device__ __forceinline__ int64_t sort_elem(int64_t block_base, int w, int k, i
     return block_base + (int64_t)w * (kSortItems * kWave) + (int64_t)k * kWave + lane;
 }
 
-template <int RB>
+// The first pass of the depth sort reads the preprocess's output in place
+// (no compaction pass): chunk c is the 4096 splats [j 4096, (j + 1) 4096) of
+// view v, c = v nbv + j; an element is valid where its visibility bit is set
+// (ntiles > 0; the bits past n are zero), its key is the record's depth bits
+// and its value the record v n + i.  Chunks in order are records in order,
+// so the pass is the stable sort of the visible records in record order.
+static_assert(kSortTile == 4096, "a chunk is one block of the visibility bit rows");
+struct VisSrc {
+    const BinsHeader *bh = nullptr;  // n_rec == 0: the buffers do not match, nothing is valid
+    const uint32_t *visbits = nullptr, *depth = nullptr;
+    int64_t n = 0, vstride = 0, nbv = 0, nbc = 0;
+};
+
+// Wavefront w's slice of chunk c: item k of lane l is splat i0 + 64 k + l.
+struct VisSlice {
+    const uint32_t *bits, *dep;
+    int64_t i0, rec0, n;
+    bool ok;
+    __device__ VisSlice(const VisSrc &vs, int64_t c, int w_)
+    {
+        const int w = __builtin_amdgcn_readfirstlane(w_);  // uniform: the bit words are scalar loads
+        const int64_t v = c / vs.nbv;
+        i0 = (c - v * vs.nbv) * kSortTile + (int64_t)w * (kSortItems * kWave);
+        n = vs.n;
+        rec0 = v * n + i0;
+        bits = vs.visbits + v * vs.vstride + (i0 >> 5);
+        dep = vs.depth + v * n;
+        ok = vs.bh->n_rec != 0;
+    }
+    // visibility bits of item k's 64 splats (two words, 8-byte aligned)
+    __device__ uint64_t word(int k) const
+    {
+        return ok ? *reinterpret_cast<const uint64_t *>(bits + 2 * k) : 0ull;
+    }
+    // depth bits of item k of this lane (clamped in range; used only where valid)
+    __device__ uint32_t key(int k, int lane) const
+    {
+        const int64_t i = i0 + (int64_t)k * kWave + lane;
+        return dep[i < n ? i : n - 1];
+    }
+};
+
+template <int RB, bool VIS = false>
 __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint32_t *keys, Count cnt, int shift,
-                                                                     int width, uint32_t *hist, int64_t hstride)
+                                                                     int width, uint32_t *hist, int64_t hstride,
+                                                                     VisSrc vs = {})
 {
     // UC count rows per wave, lane l adding into row l % UC: equal digits of
     // one wave then collide UC times less, and the odd row stride puts the
@@ -217,30 +260,44 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
     __shared__ uint32_t s_cnt[ROWS * STRIDE];
     const uint32_t dmask = (1u << width) - 1u;
     const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
-    const int64_t n = cnt.get();
+    const int64_t n = VIS ? vs.nbc * kSortTile : cnt.get();
     const int64_t nb_used = (n + kSortTile - 1) / kSortTile;  // the grid is sized for the capacity
     const int64_t chunk = (int64_t)blockIdx.x < nb_used ? xcd_chunk(blockIdx.x, nb_used) : (int64_t)blockIdx.x;
     const int64_t base = chunk * kSortTile;
     for (int i = t; i < ROWS * STRIDE; i += kSortThreads) s_cnt[i] = 0;
     __syncthreads();
-    // compiled twice: for a full chunk (all but the last) without bounds tests
-    auto count_chunk = [&](auto full_tag) {
-        constexpr bool FULL = decltype(full_tag)::value;
+    if constexpr (VIS) {
+        const VisSlice vsl(vs, chunk, w);
         uint32_t d[kSortItems];
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before any counting
-            const int64_t e = sort_elem(base, w, k, lane);
-            d[k] = FULL || e < n ? (keys[e] >> shift) & dmask : RADIX;
+            const uint32_t key = vsl.key(k, lane);
+            d[k] = (vsl.word(k) >> lane) & 1ull ? (key >> shift) & dmask : RADIX;
         }
+        // an invalid item counts into the row's padding entry RADIX (never read)
         uint32_t *row = s_cnt + (w * UC + (lane & (UC - 1))) * STRIDE;
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k)
-            if (FULL || d[k] < RADIX) atomicAdd(&row[d[k]], 1u);
-    };
-    if (base + kSortTile <= n)
-        count_chunk(std::integral_constant<bool, true>{});
-    else if (base < n)
-        count_chunk(std::integral_constant<bool, false>{});
+        for (int k = 0; k < kSortItems; ++k) atomicAdd(&row[d[k]], 1u);
+    } else {
+        // compiled twice: for a full chunk (all but the last) without bounds tests
+        auto count_chunk = [&](auto full_tag) {
+            constexpr bool FULL = decltype(full_tag)::value;
+            uint32_t d[kSortItems];
+#pragma unroll
+            for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before any counting
+                const int64_t e = sort_elem(base, w, k, lane);
+                d[k] = FULL || e < n ? (keys[e] >> shift) & dmask : RADIX;
+            }
+            uint32_t *row = s_cnt + (w * UC + (lane & (UC - 1))) * STRIDE;
+#pragma unroll
+            for (int k = 0; k < kSortItems; ++k)
+                if (FULL || d[k] < RADIX) atomicAdd(&row[d[k]], 1u);
+        };
+        if (base + kSortTile <= n)
+            count_chunk(std::integral_constant<bool, true>{});
+        else if (base < n)
+            count_chunk(std::integral_constant<bool, false>{});
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
@@ -262,12 +319,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
 // [start, end) is recorded in ranges[key]: a block's equal keys are
 // contiguous in its LDS-sorted order and in the output, and the blocks'
 // pieces of a key's range are merged with atomic min / max.
-template <int RB>
+template <int RB, bool VIS = false>
 __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, Count cnt, int shift, int width, const uint32_t *hist,
     const uint32_t *totals, int64_t hstride, const uint2 *__restrict__ gather_src, uint2 *__restrict__ gather_out,
-    uint2 *ranges, bool last)
+    uint2 *ranges, bool last, VisSrc vs = {})
 {
     constexpr int NW = kSortThreads / kWave, RADIX = 1 << RB, DPT = RADIX / kSortThreads;
     __shared__ uint32_t s_keys[kSortTile];
@@ -277,12 +334,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     __shared__ uint32_t s_tmp[NW + 1];
     const uint32_t dmask = (1u << width) - 1u;
 
-    const int64_t n = cnt.get();
+    const int64_t n = VIS ? vs.nbc * kSortTile : cnt.get();
     const int64_t nb_used = (n + kSortTile - 1) / kSortTile;  // the grid is sized for the capacity
     const int64_t chunk = (int64_t)blockIdx.x < nb_used ? xcd_chunk(blockIdx.x, nb_used) : (int64_t)blockIdx.x;
     const int64_t base = chunk * kSortTile;
     if (base >= n) return;  // uniform across the block
     const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
+    uint32_t cnt_vis = 0;  // VIS: the chunk's valid elements
     {   // thread t owns digits t * DPT .. t * DPT + DPT - 1
         uint32_t tot[DPT], sum = 0;
 #pragma unroll
@@ -304,21 +362,36 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
 
     // Loads, ranking and the scatter into LDS, compiled twice: for a chunk
     // that is full (all but the last), without the per-item bounds tests.
-    const bool full = base + kSortTile <= n;  // uniform across the block
+    const bool full = !VIS && base + kSortTile <= n;  // uniform across the block
     auto sort_chunk = [&](auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
         uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+        uint32_t vbits = 0;  // VIS: bit k set where item k is valid
         const uint64_t lt = lanemask_lt();
+        if constexpr (VIS) {
+            const VisSlice vsl(vs, chunk, w);
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
-            const int64_t e = sort_elem(base, w, k, lane);
-            key[k] = FULL || e < n ? keys_in[e] : 0u;
-            val[k] = FULL || e < n ? vals_in[e] : 0u;
+            for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
+                key[k] = vsl.key(k, lane);
+                val[k] = (uint32_t)(vsl.rec0 + (int64_t)k * kWave + lane);
+                vbits |= (uint32_t)((vsl.word(k) >> lane) & 1ull) << k;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
+                const int64_t e = sort_elem(base, w, k, lane);
+                key[k] = FULL || e < n ? keys_in[e] : 0u;
+                val[k] = FULL || e < n ? vals_in[e] : 0u;
+            }
         }
+        auto item_valid = [&](int k) -> bool {
+            if constexpr (VIS) return (vbits >> k) & 1u;
+            return FULL || sort_elem(base, w, k, lane) < n;
+        };
         // rank inside the wave: earlier items of this wave, then lower lanes of this item
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            const bool valid = FULL || sort_elem(base, w, k, lane) < n;
+            const bool valid = item_valid(k);
             const uint32_t d = (key[k] >> shift) & dmask;
             const uint64_t peers = match_digit<RB>(d, valid);
             const uint32_t before = s_wh[w][d];
@@ -340,7 +413,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
                 }
                 sum += tot[q];
             }
-            uint32_t st = block_exclusive_scan(sum, s_tmp, nullptr);
+            uint32_t st = block_exclusive_scan(sum, s_tmp, &cnt_vis);
 #pragma unroll
             for (int q = 0; q < DPT; ++q) {
                 const int dd = t * DPT + q;
@@ -355,7 +428,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            if (FULL || sort_elem(base, w, k, lane) < n) {
+            if (item_valid(k)) {
                 const uint32_t pos = s_wh[w][(key[k] >> shift) & dmask] + rank[k];
                 s_keys[pos] = key[k];
                 s_vals[pos] = val[k];
@@ -367,7 +440,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
     else
         sort_chunk(std::integral_constant<bool, false>{});
     __syncthreads();
-    const int64_t cnt_blk = n - base < kSortTile ? n - base : kSortTile;
+    const int64_t cnt_blk = VIS ? (int64_t)cnt_vis : (n - base < kSortTile ? n - base : kSortTile);
     for (int j = t; j < cnt_blk; j += kSortThreads) {
         const uint32_t kk = s_keys[j];
         const uint32_t d = (kk >> shift) & dmask;
@@ -395,11 +468,11 @@ int radix_passes(int bits) { return (bits + kMaxRadixBits - 1) / kMaxRadixBits; 
 // apply to the last pass (see radix_downsweep_kernel).
 hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Count cnt, int bit_lo,
                       int bit_hi, uint32_t *hist, uint32_t *totals, hipStream_t s, bool *result_in_b,
-                      const uint2 *gather_src = nullptr, uint2 *gather_out = nullptr, uint2 *ranges = nullptr)
+                      const uint2 *gather_src = nullptr, uint2 *gather_out = nullptr, uint2 *ranges = nullptr,
+                      const VisSrc *vis = nullptr)
 {
-    const int64_t nblocks = ceil_div(cnt.host > 0 ? cnt.host : 1, kSortTile);
-    const int64_t hstride = hist_stride(nblocks);  // histogram rows start on 16 bytes
     const int bits = bit_hi - bit_lo, passes = radix_passes(bits);
+    if (vis && (passes < 2 || bits > 8 * passes)) return hipErrorInvalidValue;  // 8-bit first pass, not the last
     bool in_b = false;
     int shift = bit_lo;
     for (int p = 0; p < passes; ++p) {
@@ -410,6 +483,21 @@ hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Co
         const uint2 *gs = last ? gather_src : nullptr;
         uint2 *go = last ? gather_out : nullptr;
         uint2 *rg = last ? ranges : nullptr;
+        if (p == 0 && vis) {  // straight from the visibility bits and depth keys
+            const int64_t nb = vis->nbc, hs = hist_stride(nb);
+            radix_upsweep_kernel<8, true><<<(unsigned)nb, kSortThreads, 0, s>>>(nullptr, cnt, shift, width, hist,
+                                                                                 hs, *vis);
+            scan_digits_kernel<<<1u << 8, kDigitScanThreads, 0, s>>>(hist, hs, Count{nullptr, nb * kSortTile},
+                                                                     totals);
+            radix_downsweep_kernel<8, true><<<(unsigned)nb, kSortThreads, 0, s>>>(
+                nullptr, nullptr, kout, vout, cnt, shift, width, hist, totals, hs, nullptr, nullptr, nullptr, false,
+                *vis);
+            in_b = !in_b;
+            shift += width;
+            continue;
+        }
+        const int64_t nblocks = ceil_div(cnt.host > 0 ? cnt.host : 1, kSortTile);
+        const int64_t hstride = hist_stride(nblocks);  // histogram rows start on 16 bytes
         if (width <= 8) {
             radix_upsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, hstride);
             scan_digits_kernel<<<1u << 8, kDigitScanThreads, 0, s>>>(hist, hstride, cnt, totals);
@@ -454,79 +542,9 @@ __global__ void finalize_counts_kernel(const ProjHeader *ph, BinsHeader *bh, int
     if (overflow_out) *overflow_out = ovf;
 }
 
-// Compaction of the visible records (tile count > 0) in record order, from
-// the visibility bits the preprocess writes: each block takes 4096
-// consecutive splats of one view (16 per thread, half a bit word); a first
-// pass counts each block's visible records (one wavefront per block, a
-// popcount of 128 words), their exclusive scan gives each block its output
-// offset, and a second pass ranks the visible records inside the block and
-// writes the (depth key, record) pairs contiguously through LDS.  Blocks go
-// view by view, so the output is in record order.
+// Blocks of 4096 records for the pair counts.
 constexpr int kCompactItems = 16;
 constexpr int kCompactTile = kSortThreads * kCompactItems;
-
-__global__ __launch_bounds__(kSortThreads) void count_visible_kernel(const BinsHeader *bh, const uint32_t *visbits,
-                                                                     int64_t vstride, int64_t nbv, int64_t nbc,
-                                                                     uint32_t *counts)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t b = (int64_t)blockIdx.x * (kSortThreads / kWave) + threadIdx.x / kWave;
-    if (b >= nbc) return;  // uniform per wavefront
-    uint32_t c = 0;
-    if (bh->n_rec) {  // 0 when the buffers do not match
-        const int64_t v = b / nbv, j = b - v * nbv;
-        const uint2 w2 = *reinterpret_cast<const uint2 *>(visbits + v * vstride + j * 128 + 2 * lane);
-        c = (uint32_t)(__popc(w2.x) + __popc(w2.y));
-    }
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
-    if (lane == 0) counts[b] = c;
-}
-
-__global__ __launch_bounds__(kSortThreads) void compact_visible_kernel(const BinsHeader *bh, const uint32_t *visbits,
-                                                                       int64_t vstride, int64_t nbv, int64_t n,
-                                                                       const uint32_t *depth,
-                                                                       const uint32_t *offsets, uint32_t *keys,
-                                                                       uint32_t *vals)
-{
-    __shared__ uint2 s_out[kCompactTile];
-    __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
-    if (bh->n_rec == 0) return;  // uniform: the buffers do not match
-    const int t = threadIdx.x;
-    const int64_t v = (int64_t)blockIdx.x / nbv, j = (int64_t)blockIdx.x - v * nbv;
-    const uint32_t bits =
-        (visbits[v * vstride + j * 128 + (t >> 1)] >> ((t & 1) * kCompactItems)) & ((1u << kCompactItems) - 1u);
-    uint32_t total;
-    uint32_t r = block_exclusive_scan((uint32_t)__popc(bits), s_tmp, &total);
-    const int64_t i_lo = j * kCompactTile + (int64_t)t * kCompactItems, rec0 = v * n + i_lo;
-    uint32_t dk[kCompactItems];
-    if (bits) {  // padding bits past n are zero
-        if ((n & 3) == 0 && i_lo + kCompactItems <= n) {  // 16-byte aligned, all in range: four vector loads
-            const uint4 *src = reinterpret_cast<const uint4 *>(depth + rec0);
-#pragma unroll
-            for (int q = 0; q < kCompactItems / 4; ++q) {
-                const uint4 u = src[q];
-                dk[4 * q] = u.x;
-                dk[4 * q + 1] = u.y;
-                dk[4 * q + 2] = u.z;
-                dk[4 * q + 3] = u.w;
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < kCompactItems; ++k) dk[k] = ((bits >> k) & 1u) ? depth[rec0 + k] : 0u;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < kCompactItems; ++k)
-        if ((bits >> k) & 1u) s_out[r++] = make_uint2(dk[k], (uint32_t)(rec0 + k));
-    __syncthreads();
-    const uint32_t out = offsets[blockIdx.x];
-    for (uint32_t q = t; q < total; q += kSortThreads) {
-        const uint2 kv = s_out[q];
-        keys[out + q] = kv.x;
-        vals[out + q] = kv.y;
-    }
-}
 
 // Tile rectangle of a sorted record's pixel box (tile sides 2^lw x 2^lh;
 // boxes are clipped to the image, so the coordinates are not negative).
@@ -753,21 +771,22 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     finalize_counts_kernel<<<1, 64, 0, s>>>(P.hdr, B.hdr, n, n_views, tile_w, tile_h, cap, (uint32_t)n_tiles,
                                             overflow_out);
 
-    // 1. compact visible records, then sort them by depth bits
-    if (R > 0) {
-        const int64_t nbv = ceil_div(n, kCompactTile), nbc = n_views * nbv, vstride = visbits_stride(n);
-        count_visible_kernel<<<(unsigned)ceil_div(nbc, kSortThreads / kWave), kSortThreads, 0, s>>>(
-            B.hdr, P.visbits, vstride, nbv, nbc, block_sum);
-        scan_partials_kernel<<<1, 1024, 0, s>>>(block_sum, nbc);
-        compact_visible_kernel<<<(unsigned)nbc, kSortThreads, 0, s>>>(B.hdr, P.visbits, vstride, nbv, n, P.depth,
-                                                                      block_sum, keys_a, vals_a);
-    }
+    // 1. sort the visible records by depth bits, stably in record order: the
+    // first pass reads the visibility bits and depth keys in place, the last
+    // also writes each sorted record's pixel box contiguously
     const Count vis_cnt{&B.hdr->n_vis, R};
     bool depth_in_b = false;
     if (R > 0) {
-        // the last pass also writes each sorted record's pixel box contiguously
+        VisSrc vs;
+        vs.bh = B.hdr;
+        vs.visbits = P.visbits;
+        vs.depth = P.depth;
+        vs.n = n;
+        vs.vstride = visbits_stride(n);
+        vs.nbv = ceil_div(n, kSortTile);
+        vs.nbc = n_views * vs.nbv;
         e = radix_sort(keys_a, vals_a, keys_b, vals_b, vis_cnt, 0, 32, hist, totals, s, &depth_in_b,
-                       (const uint2 *)P.bbox, sorted_box);
+                       (const uint2 *)P.bbox, sorted_box, nullptr, &vs);
         if (e != hipSuccess) return e;
     }
     const uint32_t *sorted_rec = depth_in_b ? vals_b : vals_a;
