@@ -635,7 +635,7 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, c
 {
     __shared__ uint32_t s_off[257];
     __shared__ uint32_t s_rec[256], s_row0[256], s_tx[256];
-    __shared__ uint16_t s_w[256];
+    __shared__ uint2 s_w[256];  // (tile columns w, bits of the float 1 / w)
     __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
     __shared__ uint8_t s_flag[256 / kWave][kWave];
     const int64_t nvis = bh->overflow ? 0 : (int64_t)bh->n_vis;  // nothing is emitted on overflow
@@ -652,7 +652,7 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, c
         s_rec[t] = rec;
         s_row0[t] = (uint32_t)V.tile_offset + (uint32_t)(r.ty0 * V.tiles_x + r.tx0);
         s_tx[t] = (uint32_t)V.tiles_x;
-        s_w[t] = (uint16_t)r.w;
+        s_w[t] = make_uint2((uint32_t)r.w, __float_as_uint(__builtin_amdgcn_rcpf((float)r.w)));
     }
     uint32_t total;
     const uint32_t off = block_exclusive_scan(cnt, s_tmp, &total);
@@ -662,22 +662,25 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, c
     if (t == 0) s_off[cntb] = total;
     __syncthreads();
     const uint64_t cap = bh->n_pairs;  // pairs are only emitted below the binned count
-    const uint32_t nsteps = (total + kWave - 1) / kWave, per = (nsteps + 3) / 4;
-    const uint32_t c0 = w * per, c1 = c0 + per < nsteps ? c0 + per : nsteps;
+    // the step range, the step's first pair and its record are wave-uniform
+    // (scalar registers and loop control)
+    const uint32_t tot_u = __builtin_amdgcn_readfirstlane(total);
+    const uint32_t nsteps = (tot_u + kWave - 1) / kWave, per = (nsteps + 3) / 4;
+    const uint32_t c0 = __builtin_amdgcn_readfirstlane(w) * per, c1 = c0 + per < nsteps ? c0 + per : nsteps;
     int r_cur = -1;
     const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
     for (uint32_t c = c0; c < c1; ++c) {
         const uint32_t q0 = c * kWave;
         int r0;
-        if (r_cur < 0) {  // the record holding pair q0 (wave-uniform)
+        if (r_cur < 0) {  // the record holding pair q0
             int lo = 0, hi = cntb - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= q0) lo = mid; else hi = mid - 1;
+                if (__builtin_amdgcn_readfirstlane(s_off[mid]) <= q0) lo = mid; else hi = mid - 1;
             }
             r0 = lo;
         } else {
-            r0 = (r_cur + 1 < cntb && s_off[r_cur + 1] <= q0) ? r_cur + 1 : r_cur;
+            r0 = (r_cur + 1 < cntb && __builtin_amdgcn_readfirstlane(s_off[r_cur + 1]) <= q0) ? r_cur + 1 : r_cur;
         }
         s_flag[w][lane] = 0;
         __builtin_amdgcn_wave_barrier();
@@ -694,20 +697,17 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, c
         if (q < total && gp < cap) {
             // (dy, dx) of the pair inside the record's tile rectangle: the quotient
             // from the float reciprocal is off by at most one (local < 2^22)
-            const uint32_t local = q - s_off[r], wr = s_w[r];
-            uint32_t dy = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)wr));
+            const uint2 wrr = s_w[r];
+            const uint32_t local = q - s_off[r], wr = wrr.x;
+            uint32_t dy = (uint32_t)((float)local * __uint_as_float(wrr.y));
             int32_t rem = (int32_t)local - (int32_t)(dy * wr);
-            if (rem < 0) {
-                dy -= 1;
-                rem += (int32_t)wr;
-            } else if (rem >= (int32_t)wr) {
-                dy += 1;
-                rem -= (int32_t)wr;
-            }
+            const bool neg = rem < 0, big = rem >= (int32_t)wr;  // at most one holds
+            dy = dy + (big ? 1u : 0u) - (neg ? 1u : 0u);
+            rem += neg ? (int32_t)wr : (big ? -(int32_t)wr : 0);
             pkeys[gp] = s_row0[r] + dy * s_tx[r] + (uint32_t)rem;
             pvals[gp] = s_rec[r];
         }
-        r_cur = __shfl(r, kWave - 1, kWave);
+        r_cur = __builtin_amdgcn_readlane(r, kWave - 1);
         __builtin_amdgcn_wave_barrier();
     }
 }
