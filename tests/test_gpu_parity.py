@@ -100,6 +100,20 @@ def test_binning_bit_exact_tiny(oracle, tile):
     _check_bins(oracle, out, cams, 400, "oracle", *tile)
 
 
+@pytest.mark.parametrize("n", [4095, 4097, 8193])
+def test_binning_bit_exact_chunk_boundaries(oracle, n):
+    """Splat counts around the 4096-splat chunks of the depth sort's first
+    pass (which reads each view's visibility bits and depth keys in place):
+    a partial last chunk, one splat past a chunk, three views."""
+    s = tiny_scene(n, 17 + n % 7)
+    cams = [scenes.look_at_camera([0.5, 0.3, -5.0], 75, 53), scenes.camera(37, 29, f=30.0),
+            scenes.look_at_camera([-1.0, 0.4, -4.0], 64, 64)]
+    out = gpu_render(s, cams, cfg(16, 16))
+    out["scene"] = s
+    _check_bins(oracle, out, cams, n, "gpu", 16, 16)
+    _check_bins(oracle, out, cams, n, "oracle", 16, 16)
+
+
 def test_binning_bit_exact_c1(oracle):
     s, cams = scenes.config1()
     out = gpu_render(s, cams)
