@@ -57,7 +57,7 @@ struct BinsHeader {
     uint32_t n_pairs;      // pairs actually binned (0 on overflow)
     uint32_t n_tiles;
     uint32_t queue[4];     // persistent work queues: fwd head, fwd done, bwd head, bwd done
-    uint32_t n_rec;        // records the compaction reads: n * n_views, 0 on a mismatch
+    uint32_t n_rec;        // records the depth sort's first pass reads: n * n_views, 0 on a mismatch
     int32_t n_views, tile_w, tile_h;
     int64_t n;             // what the lists were built for
     uint32_t pad[18];

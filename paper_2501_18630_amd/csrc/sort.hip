@@ -3,9 +3,11 @@
 // Sec. 3.2 composites the primitives overlapping a pixel "after sorting by
 // depth".  Instead of one wide radix sort of (tile | depth) keys over all
 // pairs, the order is built in two narrow stable sorts:
-//   1. compact the visible (view, splat) records and radix-sort them by the
-//      fp32 bits of their depth (32 bits, over P records); stability keeps
-//      equal depths in record order, i.e. by splat index within a view;
+//   1. radix-sort the visible (view, splat) records by the fp32 bits of
+//      their depth (32 bits; the first pass reads the visibility bits and
+//      depth keys of all records in place, the others the P visible ones);
+//      stability keeps equal depths in record order, i.e. by splat index
+//      within a view;
 //   2. emit one (global tile id, record) pair per overlapped tile, walking
 //      the records in depth order, and radix-sort the pairs by tile id only
 //      (ceil(log2 tiles) bits, over K pairs); stability keeps the depth
@@ -13,7 +15,7 @@
 // The result is exactly the lexicographic (view, tile, depth bits, splat id)
 // order, at 2-3 narrow passes over the K pairs instead of 6-7 wide ones.
 //
-// The radix sort is a classic LSD sort with 8-bit digits: per-block digit
+// The radix sort is a classic LSD sort with 8- or 9-bit digits: per-block digit
 // histograms (upsweep), a scan of each digit's counts over the blocks plus
 // the digit totals, and a stable scatter (downsweep) that ranks each block's keys
 // with wave ballots and per-wave digit counts in LDS (no LDS atomics, one
