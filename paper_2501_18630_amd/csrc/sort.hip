@@ -236,11 +236,9 @@ struct VisSlice {
         dep = vs.depth + v * n;
         ok = vs.bh->n_rec != 0;
     }
-    // visibility bits of item k's 64 splats (two words, 8-byte aligned)
-    __device__ uint64_t word(int k) const
-    {
-        return ok ? *reinterpret_cast<const uint64_t *>(bits + 2 * k) : 0ull;
-    }
+    // visibility bits of item k's 64 splats (two words, 8-byte aligned);
+    // read only when ok
+    __device__ uint64_t word(int k) const { return *reinterpret_cast<const uint64_t *>(bits + 2 * k); }
     // depth bits of item k of this lane (clamped in range; used only where valid)
     __device__ uint32_t key(int k, int lane) const
     {
@@ -271,10 +269,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
     if constexpr (VIS) {
         const VisSlice vsl(vs, chunk, w);
         uint32_t d[kSortItems];
+        if (vsl.ok) {  // uniform; on a buffer mismatch nothing is read and nothing counts
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before any counting
-            const uint32_t key = vsl.key(k, lane);
-            d[k] = (vsl.word(k) >> lane) & 1ull ? (key >> shift) & dmask : RADIX;
+            for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before any counting
+                const uint32_t key = vsl.key(k, lane);
+                d[k] = (vsl.word(k) >> lane) & 1ull ? (key >> shift) & dmask : RADIX;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSortItems; ++k) d[k] = RADIX;
         }
         // an invalid item counts into the row's padding entry RADIX (never read)
         uint32_t *row = s_cnt + (w * UC + (lane & (UC - 1))) * STRIDE;
@@ -373,10 +376,16 @@ __global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
         if constexpr (VIS) {
             const VisSlice vsl(vs, chunk, w);
 #pragma unroll
-            for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
-                key[k] = vsl.key(k, lane);
+            for (int k = 0; k < kSortItems; ++k) {
+                key[k] = 0u;
                 val[k] = (uint32_t)(vsl.rec0 + (int64_t)k * kWave + lane);
-                vbits |= (uint32_t)((vsl.word(k) >> lane) & 1ull) << k;
+            }
+            if (vsl.ok) {  // uniform; on a buffer mismatch nothing is read and nothing is valid
+#pragma unroll
+                for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
+                    key[k] = vsl.key(k, lane);
+                    vbits |= (uint32_t)((vsl.word(k) >> lane) & 1ull) << k;
+                }
             }
         } else {
 #pragma unroll
