@@ -324,13 +324,18 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
 // [start, end) is recorded in ranges[key]: a block's equal keys are
 // contiguous in its LDS-sorted order and in the output, and the blocks'
 // pieces of a key's range are merged with atomic min / max.
-template <int RB, bool VIS = false>
-__global__ __launch_bounds__(kSortThreads) void radix_downsweep_kernel(
+// LAST: the sort's last pass (values only; gather and ranges).  With 8-bit
+// digits it is held to 128 VGPRs for a fourth wavefront per SIMD (measured
+// faster there, not in the other passes; 9-bit passes are held to three by
+// their LDS).
+template <int RB, bool VIS = false, bool LAST = false>
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LAST && RB == 8 ? 4 : 1))) void radix_downsweep_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, Count cnt, int shift, int width, const uint32_t *hist,
     const uint32_t *totals, int64_t hstride, const uint2 *__restrict__ gather_src, uint2 *__restrict__ gather_out,
-    uint2 *ranges, bool last, VisSrc vs = {})
+    uint2 *ranges, VisSrc vs = {})
 {
+    constexpr bool last = LAST;
     constexpr int NW = kSortThreads / kWave, RADIX = 1 << RB, DPT = RADIX / kSortThreads;
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
@@ -501,8 +506,7 @@ hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Co
             scan_digits_kernel<<<1u << 8, kDigitScanThreads, 0, s>>>(hist, hs, Count{nullptr, nb * kSortTile},
                                                                      totals);
             radix_downsweep_kernel<8, true><<<(unsigned)nb, kSortThreads, 0, s>>>(
-                nullptr, nullptr, kout, vout, cnt, shift, width, hist, totals, hs, nullptr, nullptr, nullptr, false,
-                *vis);
+                nullptr, nullptr, kout, vout, cnt, shift, width, hist, totals, hs, nullptr, nullptr, nullptr, *vis);
             in_b = !in_b;
             shift += width;
             continue;
@@ -512,13 +516,21 @@ hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Co
         if (width <= 8) {
             radix_upsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, hstride);
             scan_digits_kernel<<<1u << 8, kDigitScanThreads, 0, s>>>(hist, hstride, cnt, totals);
-            radix_downsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg, last);
+            if (last)
+                radix_downsweep_kernel<8, false, true><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg);
+            else
+                radix_downsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg);
         } else {
             radix_upsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, hstride);
             scan_digits_kernel<<<1u << 9, kDigitScanThreads, 0, s>>>(hist, hstride, cnt, totals);
-            radix_downsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg, last);
+            if (last)
+                radix_downsweep_kernel<9, false, true><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg);
+            else
+                radix_downsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg);
         }
         in_b = !in_b;
         shift += width;
