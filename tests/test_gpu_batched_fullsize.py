@@ -298,6 +298,32 @@ def test_fullsize_crop_gradient_batched(oracle, c3):
         assert not np.any(g[k][far]), k
 
 
+def test_config2_crop_gradient(oracle, c2):
+    """Config 2 (one 1600x1064 view, 1.5 M clustered splats): dL/dimage
+    non-zero on a 48x48 crop at the image centre, where the clusters overlap
+    most; every splat that reaches the crop matches the oracle, every other
+    one gets exactly zero."""
+    import torch
+    run = c2
+    cam = run.cams[0]
+    x0, y0, w = cam["width"] // 2 - 24, cam["height"] // 2 - 24, 48
+    dls = [np.zeros((3, cam["height"], cam["width"]), np.float32)]
+    dls[0][:, y0:y0 + w, x0:x0 + w] = np.random.default_rng(29).standard_normal((3, w, w))
+    out, rast = run.out, run.rast
+    dl = torch.as_tensor(dls[0]).reshape(-1).cuda()
+    grads = {k: torch.zeros_like(out["params"][k]) for k in PARAMS}
+    rast.backward(out["params"], dl, out["T_t"], out["last_t"], grads)
+    g = {k: grads[k].cpu().numpy().astype(np.float64) for k in PARAMS}
+    near, g_ref, a_ref, c_ref = _crop_grads(oracle, run, [(0, x0, y0, w)], dls)
+    assert near.size > 100
+    mine = {k: g[k][near] for k in PARAMS}
+    _report_scales("config 2 crop gradient", mine, g_ref, a_ref, c_ref)
+    assert_grads_close(mine, g_ref, a_ref)
+    far = np.setdiff1d(np.arange(run.n), near)
+    for k in PARAMS:
+        assert not np.any(g[k][far]), k
+
+
 def test_config4_crop_gradient_store(oracle, c4):
     """Config 4's training-step reverse pass: the gradient store over all 32
     views, with dL/dimage non-zero on 48x48 crops of two views, so that a
