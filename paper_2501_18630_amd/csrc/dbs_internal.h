@@ -81,7 +81,7 @@ static_assert(sizeof(RasterRec) == 64, "RasterRec layout");
 __host__ __device__ inline int64_t visbits_stride(int64_t n) { return (n + 4095) / 4096 * 128; }
 
 struct ProjLayout {
-    size_t header, views, rec, bbox, depth, ntiles, visbits, gradmask, sgrad, total;
+    size_t header, views, rec, bbox, depth, ntiles, visbits, gradmask, sgrad, blockcnt, total;
 };
 inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     ProjLayout L;
@@ -95,6 +95,7 @@ inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     L.visbits = o; o = align_up(o + 4 * (size_t)n_views * (size_t)visbits_stride(n));
     L.gradmask = o; o = align_up(o + 8 * (size_t)n * (size_t)((n_views + 63) / 64));
     L.sgrad = o;  o = align_up(o + 64 * R);   // screen-space gradient, one 64-byte line per record
+    L.blockcnt = o; o = align_up(o + 16 * (size_t)((n + 255) / 256));  // per-workgroup counts of the preprocess
     L.total = o;
     return L;
 }
@@ -210,6 +211,9 @@ struct ProjPtrs {
     // sent gradient to record (v, i)'s line of sgrad; cleared with the line
     uint64_t *gradmask;
     float4 *sgrad;  // [R][4]: dmu'(2), dA(3), do, db, dcolour(3), 6 unused
+    // [ceil(n / 256)][2]: visible records and pairs of each preprocess
+    // workgroup, summed into hdr->counts by one workgroup afterwards
+    uint64_t *blockcnt;
 };
 inline ProjPtrs proj_ptrs(void *base, int64_t n, int32_t n_views) {
     ProjLayout L = proj_layout(n, n_views);
@@ -224,6 +228,7 @@ inline ProjPtrs proj_ptrs(void *base, int64_t n, int32_t n_views) {
     p.visbits = (uint32_t *)(b + L.visbits);
     p.gradmask = (uint64_t *)(b + L.gradmask);
     p.sgrad = (float4 *)(b + L.sgrad);
+    p.blockcnt = (uint64_t *)(b + L.blockcnt);
     return p;
 }
 
