@@ -420,7 +420,9 @@ dbs_status dbs_projected_state(void *projected, int64_t n, int32_t n_views, void
  *   pair_rec   [pair_capacity] uint32 record r = v n + i per pair, sorted
  *   tile_range [n_tiles] uint32x2 (start, end) into pair_rec per global tile
  *              (view tiles are numbered consecutively, view-major, row-major)
- *   tile_order [n_tiles] uint32 work order of global tiles
+ *   tile_order [n_tiles] uint32 work order of global tiles, heaviest pair
+ *              count class first (a class per count below 16, then 16 per
+ *              octave), ties in tile order
  * *n_tiles receives the total tile count of all views. */
 dbs_status dbs_bins_layout(void *bins, int64_t pair_capacity, const dbs_camera *cams /*[host]*/,
                            int32_t n_views, const dbs_raster_cfg *cfg /*[host]*/,

@@ -279,10 +279,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
 #pragma unroll
             for (int k = 0; k < kSortItems; ++k) d[k] = RADIX;
         }
-        // an invalid item counts into the row's padding entry RADIX (never read)
+        // an invalid item is not counted: about half the items of a view are
+        // invisible, and adding them all into one padding entry serialised
+        // the wave's atomics on that address
         uint32_t *row = s_cnt + (w * UC + (lane & (UC - 1))) * STRIDE;
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) atomicAdd(&row[d[k]], 1u);
+        for (int k = 0; k < kSortItems; ++k)
+            if (d[k] < RADIX) atomicAdd(&row[d[k]], 1u);
     } else {
         // compiled twice: for a full chunk (all but the last) without bounds tests
         auto count_chunk = [&](auto full_tag) {
@@ -749,8 +752,11 @@ __global__ void fill_ranges_kernel(uint2 *ranges, int64_t n_tiles)
     if (i < n_tiles) ranges[i] = make_uint2(0xffffffffu, 0u);
 }
 
-// Heaviest tiles first: key = 0xffff - min(pairs, 0xffff).  Also turns the
-// range of a tile no pair reached, still (~0, 0), into (0, 0).
+// Heaviest tiles first, by an 8-bit cost class so that one radix pass sorts
+// them: the pair count c itself below 16, above it 16 classes per octave
+// (the leading five bits of c), with c capped at 0xffff (class 207); key =
+// 255 - class, ties in tile order.  Also turns the range of a tile no pair
+// reached, still (~0, 0), into (0, 0).
 __global__ void tile_cost_keys_kernel(uint2 *ranges, int64_t n_tiles, uint32_t *keys, uint32_t *vals)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -760,8 +766,14 @@ __global__ void tile_cost_keys_kernel(uint2 *ranges, int64_t n_tiles, uint32_t *
         r = make_uint2(0u, 0u);
         ranges[t] = r;
     }
-    const uint32_t c = r.y - r.x;
-    keys[t] = 0xffffu - (c < 0xffffu ? c : 0xffffu);
+    uint32_t c = r.y - r.x;
+    c = c < 0xffffu ? c : 0xffffu;
+    uint32_t cls = c;
+    if (c >= 16u) {
+        const int e = 31 - __builtin_clz(c);  // 4 .. 15
+        cls = (uint32_t)(e - 3) * 16u + ((c >> (e - 4)) & 15u);
+    }
+    keys[t] = 255u - cls;
     vals[t] = (uint32_t)t;
 }
 
@@ -843,13 +855,13 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
         fill_u32_kernel<<<(unsigned)ceil_div(2 * n_tiles, 256), 256, 0, s>>>((uint32_t *)B.tile_range,
                                                                              2 * n_tiles, 0u);
     }
-    // 4. work order: heaviest tiles first (two 8-bit passes, result back in the a buffers)
+    // 4. work order: heaviest tiles first (one 8-bit pass from the tmp buffers into tile_order)
     if (n_tiles > 0) {
         tile_cost_keys_kernel<<<(unsigned)ceil_div(n_tiles, 256), 256, 0, s>>>(B.tile_range, n_tiles, tkeys_a,
-                                                                               B.tile_order);
+                                                                               tvals_tmp);
         bool in_b = false;
-        e = radix_sort(tkeys_a, B.tile_order, tkeys_b, tvals_tmp, Count{nullptr, n_tiles}, 0, 16, hist,
-                       totals, s, &in_b);
+        e = radix_sort(tkeys_a, tvals_tmp, tkeys_b, B.tile_order, Count{nullptr, n_tiles}, 0, 8, hist, totals,
+                       s, &in_b);
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();

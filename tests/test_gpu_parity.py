@@ -57,6 +57,15 @@ def test_preprocess_matches_oracle(oracle, which):
 
 # ---------------------------------------------------------------- binning
 
+def _cost_class(c):
+    """The work order's cost class of a tile with c pairs (c capped at 0xffff):
+    c itself below 16, then 16 classes per octave, 16 s + (c >> s) with s the
+    bit length of c less five."""
+    c = np.minimum(np.asarray(c, np.int64), 0xFFFF)
+    s = np.maximum(np.floor(np.log2(np.maximum(c, 1))).astype(np.int64) - 4, 0)
+    return 16 * s + (c >> s)
+
+
 def _check_bins(oracle, out, cams, n, bbox_src, tw, th):
     rast = out["rast"]
     b = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in rast.bins_arrays().items()}
@@ -83,11 +92,12 @@ def _check_bins(oracle, out, cams, n, bbox_src, tw, th):
                 raise AssertionError(f"view {v} tile {t}: {got[:8]} vs {ref[:8]}")
         total += ids.size
     assert total == int(rec["counts"][1])
-    # work order is a permutation, heaviest first
+    # work order is a permutation, heaviest cost class first, ties in tile order
     order = b["tile_order"].astype(np.int64)
     assert np.array_equal(np.sort(order), np.arange(b["n_tiles"]))
-    cnt = np.minimum(b["tile_range"][:, 1] - b["tile_range"][:, 0], 0xFFFF)[order]
-    assert np.all(np.diff(cnt) <= 0)
+    cls = _cost_class(b["tile_range"][:, 1].astype(np.int64) - b["tile_range"][:, 0])[order]
+    assert np.all(np.diff(cls) <= 0)
+    assert np.all(np.diff(order)[np.diff(cls) == 0] > 0)
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8), (16, 8), (32, 16)])
