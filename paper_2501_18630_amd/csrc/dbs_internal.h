@@ -80,8 +80,24 @@ static_assert(sizeof(RasterRec) == 64, "RasterRec layout");
 // Words per view of the visibility bits: whole blocks of 4096 splats.
 __host__ __device__ inline int64_t visbits_stride(int64_t n) { return (n + 4095) / 4096 * 128; }
 
+// A record's tile rectangle in 32 bits, written by the preprocess and
+// carried through the depth sort beside each record: first column tx0 in
+// bits 0-9, first row ty0 in 10-19, w - 1 in 20-25, h - 1 in 26-31.  A
+// rectangle that reaches past column or row 1023 or spans more than 64 tiles
+// is stored as kRectEscape (no packed rectangle has that value: tx0 = 1023
+// with w = 64 would reach column 1086), and its consumers take it from the
+// record's pixel box instead.
+constexpr uint32_t kRectEscape = 0xffffffffu;
+__device__ __forceinline__ uint32_t pack_tile_rect(int tx0, int ty0, int w, int h)
+{
+    const bool fits = (uint32_t)tx0 + (uint32_t)w <= 1024u && (uint32_t)ty0 + (uint32_t)h <= 1024u &&
+                      (uint32_t)(w - 1) < 64u && (uint32_t)(h - 1) < 64u;
+    return fits ? (uint32_t)tx0 | (uint32_t)ty0 << 10 | (uint32_t)(w - 1) << 20 | (uint32_t)(h - 1) << 26
+                : kRectEscape;
+}
+
 struct ProjLayout {
-    size_t header, views, rec, bbox, depth, ntiles, visbits, gradmask, sgrad, blockcnt, total;
+    size_t header, views, rec, bbox, depth, ntiles, rect, visbits, gradmask, sgrad, blockcnt, total;
 };
 inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     ProjLayout L;
@@ -92,6 +108,7 @@ inline ProjLayout proj_layout(int64_t n, int32_t n_views) {
     L.bbox = o;   o = align_up(o + 8 * R);
     L.depth = o;  o = align_up(o + 4 * R);
     L.ntiles = o; o = align_up(o + 4 * R);
+    L.rect = o;   o = align_up(o + 4 * R);
     L.visbits = o; o = align_up(o + 4 * (size_t)n_views * (size_t)visbits_stride(n));
     L.gradmask = o; o = align_up(o + 8 * (size_t)n * (size_t)((n_views + 63) / 64));
     L.sgrad = o;  o = align_up(o + 64 * R);   // screen-space gradient, one 64-byte line per record
@@ -130,7 +147,7 @@ inline int64_t hist_stride(int64_t nblocks) { return (nblocks + 3) / 4 * 4; }
 struct WorkLayout {
     // bin/sort phase
     size_t keys_a, vals_a, keys_b, vals_b, block_sum, group_sum, pkeys_a, pkeys_b, pvals_b, hist, totals,
-        tkeys_a, tvals_a, tkeys_b, sorted_box, sort_total;
+        tkeys_a, tvals_a, tkeys_b, rect_a, rect_b, sort_total;
     size_t total;
     int64_t hist_blocks;  // max sort blocks of any sort
 };
@@ -162,7 +179,9 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     L.tkeys_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
     L.tvals_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
     L.tkeys_b = o;  o = align_up(o + 4 * (size_t)n_tiles);
-    L.sorted_box = o; o = align_up(o + 8 * R);
+    // packed tile rectangles carried through the depth sort (ping-pong)
+    L.rect_a = o;   o = align_up(o + 4 * R);
+    L.rect_b = o;   o = align_up(o + 4 * R);
     L.sort_total = o;
     L.total = L.sort_total;
     return L;
@@ -203,6 +222,7 @@ struct ProjPtrs {
     RasterRec *rec;
     short4 *bbox;
     uint32_t *depth, *ntiles;
+    uint32_t *rect;  // [R] packed tile rectangle (pack_tile_rect), written where ntiles > 0
     // [V][visbits_stride(n)]: bit i % 32 of word i / 32 of row v set when record
     // (v, i) has ntiles > 0; a row covers whole blocks of 4096 splats (the
     // padding bits stay zero)
@@ -225,6 +245,7 @@ inline ProjPtrs proj_ptrs(void *base, int64_t n, int32_t n_views) {
     p.bbox = (short4 *)(b + L.bbox);
     p.depth = (uint32_t *)(b + L.depth);
     p.ntiles = (uint32_t *)(b + L.ntiles);
+    p.rect = (uint32_t *)(b + L.rect);
     p.visbits = (uint32_t *)(b + L.visbits);
     p.gradmask = (uint64_t *)(b + L.gradmask);
     p.sgrad = (float4 *)(b + L.sgrad);

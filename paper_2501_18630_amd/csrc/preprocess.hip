@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
                 tc[r] = W[3 * r] * mu[0] + W[3 * r + 1] * mu[1] + W[3 * r + 2] * mu[2] + (double)V.t[r];
             const float depth_f = (float)tc[2];
             P.depth[rec] = __float_as_uint(depth_f);
-            uint32_t ntiles = 0;
+            uint32_t ntiles = 0, rect = kRectEscape;
             short4 bb = make_short4(0, -1, 0, -1);
             if (ok && tc[2] > (double)V.near_plane) {
                 const double tx = tc[0], ty = tc[1], tz = tc[2];
@@ -242,7 +242,9 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
                     if (xl <= xh && yl <= yh) {
                         const int ixl = (int)xl, ixh = (int)xh, iyl = (int)yl, iyh = (int)yh;
                         bb = make_short4((short)ixl, (short)ixh, (short)iyl, (short)iyh);
-                        ntiles = (uint32_t)(((ixh >> lw) - (ixl >> lw) + 1) * ((iyh >> lh) - (iyl >> lh) + 1));
+                        const int tw_ = (ixh >> lw) - (ixl >> lw) + 1, th_ = (iyh >> lh) - (iyl >> lh) + 1;
+                        ntiles = (uint32_t)(tw_ * th_);
+                        rect = pack_tile_rect(ixl >> lw, iyl >> lh, tw_, th_);
                         const double idet = 1.0 / (GSH ? 9.0 * det : det);
                         RasterRec rr;
                         rr.cx = mx;
@@ -317,6 +319,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(SplatPtrs sp, const flo
             }
             P.bbox[rec] = bb;
             P.ntiles[rec] = ntiles;
+            P.rect[rec] = rect;
             {   // the wavefront's 64 visibility bits of this view (i0 is a multiple of 64)
                 const uint64_t vbits = __ballot(ntiles > 0);
                 if (lane == 0)

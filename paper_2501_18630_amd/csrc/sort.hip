@@ -207,22 +207,49 @@ __device__ __forceinline__ int64_t sort_elem(int64_t block_base, int w, int k, i
     return block_base + (int64_t)w * (kSortItems * kWave) + (int64_t)k * kWave + lane;
 }
 
+// Tile rectangle of a record's pixel box (tile sides 2^lw x 2^lh;
+// boxes are clipped to the image, so the coordinates are not negative).
+struct TileRect {
+    int tx0, ty0, w, h;
+};
+__device__ __forceinline__ TileRect tile_rect(short4 b, int lw, int lh)
+{
+    TileRect r;
+    r.tx0 = b.x >> lw;
+    r.ty0 = b.z >> lh;
+    r.w = (b.y >> lw) - r.tx0 + 1;
+    r.h = (b.w >> lh) - r.ty0 + 1;
+    return r;
+}
+
+// The packed tile rectangle (pack_tile_rect) as a TileRect.
+__device__ __forceinline__ TileRect unpack_rect(uint32_t p)
+{
+    TileRect r;
+    r.tx0 = (int)(p & 1023u);
+    r.ty0 = (int)((p >> 10) & 1023u);
+    r.w = (int)((p >> 20) & 63u) + 1;
+    r.h = (int)(p >> 26) + 1;
+    return r;
+}
+
 // The first pass of the depth sort reads the preprocess's output in place
 // (no compaction pass): chunk c is the 4096 splats [j 4096, (j + 1) 4096) of
 // view v, c = v nbv + j; an element is valid where its visibility bit is set
-// (ntiles > 0; the bits past n are zero), its key is the record's depth bits
-// and its value the record v n + i.  Chunks in order are records in order,
-// so the pass is the stable sort of the visible records in record order.
+// (ntiles > 0; the bits past n are zero), its key is the record's depth bits,
+// its value the record v n + i and its carried word the record's packed tile
+// rectangle.  Chunks in order are records in order, so the pass is the
+// stable sort of the visible records in record order.
 static_assert(kSortTile == 4096, "a chunk is one block of the visibility bit rows");
 struct VisSrc {
     const BinsHeader *bh = nullptr;  // n_rec == 0: the buffers do not match, nothing is valid
-    const uint32_t *visbits = nullptr, *depth = nullptr;
+    const uint32_t *visbits = nullptr, *depth = nullptr, *rect = nullptr;
     int64_t n = 0, vstride = 0, nbv = 0, nbc = 0;
 };
 
 // Wavefront w's slice of chunk c: item k of lane l is splat i0 + 64 k + l.
 struct VisSlice {
-    const uint32_t *bits, *dep;
+    const uint32_t *bits, *dep, *rct;
     int64_t i0, rec0, n;
     bool ok;
     __device__ VisSlice(const VisSrc &vs, int64_t c, int w_)
@@ -234,6 +261,7 @@ struct VisSlice {
         rec0 = v * n + i0;
         bits = vs.visbits + v * vs.vstride + (i0 >> 5);
         dep = vs.depth + v * n;
+        rct = vs.rect + v * n;
         ok = vs.bh->n_rec != 0;
     }
     // visibility bits of item k's 64 splats (two words, 8-byte aligned);
@@ -244,6 +272,12 @@ struct VisSlice {
     {
         const int64_t i = i0 + (int64_t)k * kWave + lane;
         return dep[i < n ? i : n - 1];
+    }
+    // packed tile rectangle of item k of this lane (clamped likewise)
+    __device__ uint32_t rect(int k, int lane) const
+    {
+        const int64_t i = i0 + (int64_t)k * kWave + lane;
+        return rct[i < n ? i : n - 1];
     }
 };
 
@@ -320,29 +354,33 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
 // The output offset of digit d of this chunk is the digit's base (the
 // exclusive scan of the digit totals) plus the chunk's entry of the
 // per-digit scanned histogram.  The last pass writes no keys (they are not
-// needed afterwards).  In the last pass, if gather_src is set, it also writes
-// gather_out[o] = gather_src[value] at each output position o (a per-value
-// field carried through the sort), and if ranges is set (a sort by the full
-// key, ranges[] holding (~0, 0) before), each key's output range
-// [start, end) is recorded in ranges[key]: a block's equal keys are
-// contiguous in its LDS-sorted order and in the output, and the blocks'
+// needed afterwards).  AUX: a second 32-bit value per element is carried
+// beside the first (aux_in to aux_out; in the VIS pass, the packed tile
+// rectangle of the record's pixel box).  In the last pass, if ranges is set
+// (a sort by the full key, ranges[] holding (~0, 0) before), each key's
+// output range [start, end) is recorded in ranges[key]: a block's equal keys
+// are contiguous in its LDS-sorted order and in the output, and the blocks'
 // pieces of a key's range are merged with atomic min / max.
-// LAST: the sort's last pass (values only; gather and ranges).  With 8-bit
-// digits it is held to 128 VGPRs for a fourth wavefront per SIMD (measured
-// faster there, not in the other passes; 9-bit passes are held to three by
-// their LDS).
-template <int RB, bool VIS = false, bool LAST = false>
-__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LAST && RB == 8 ? 4 : 1))) void radix_downsweep_kernel(
+// LAST: the sort's last pass (values only; ranges).  With 8-bit digits and
+// no carried word it is held to 128 VGPRs for a fourth wavefront per SIMD
+// (measured faster there, not in the other passes; 9-bit passes are held to
+// three by their LDS).
+template <int RB, bool VIS = false, bool LAST = false, bool AUX = false>
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LAST && RB == 8 && !AUX ? 4 : 1))) void radix_downsweep_kernel(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     uint32_t *__restrict__ vals_out, Count cnt, int shift, int width, const uint32_t *hist,
-    const uint32_t *totals, int64_t hstride, const uint2 *__restrict__ gather_src, uint2 *__restrict__ gather_out,
+    const uint32_t *totals, int64_t hstride, const uint32_t *__restrict__ aux_in, uint32_t *__restrict__ aux_out,
     uint2 *ranges, VisSrc vs = {})
 {
     constexpr bool last = LAST;
     constexpr int NW = kSortThreads / kWave, RADIX = 1 << RB, DPT = RADIX / kSortThreads;
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
-    __shared__ uint32_t s_wh[NW][RADIX];   // per-wave digit counts, then per-wave offsets
+    __shared__ uint32_t s_aux[AUX ? kSortTile : 1];
+    // per-wave digit counts, then per-wave offsets (below 4096); 16-bit where
+    // a word is carried, so that three workgroups fit in a CU's LDS
+    using WH = std::conditional_t<AUX, uint16_t, uint32_t>;
+    __shared__ WH s_wh[NW][RADIX];
     __shared__ uint32_t s_goff[RADIX];
     __shared__ uint32_t s_tmp[NW + 1];
     const uint32_t dmask = (1u << width) - 1u;
@@ -378,21 +416,24 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
     const bool full = !VIS && base + kSortTile <= n;  // uniform across the block
     auto sort_chunk = [&](auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
-        uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+        uint32_t key[kSortItems], val[kSortItems], rank[kSortItems], aux[AUX ? kSortItems : 1];
         uint32_t vbits = 0;  // VIS: bit k set where item k is valid
         const uint64_t lt = lanemask_lt();
         if constexpr (VIS) {
+            static_assert(AUX, "the first depth pass carries the tile rectangles");
             const VisSlice vsl(vs, chunk, w);
 #pragma unroll
             for (int k = 0; k < kSortItems; ++k) {
                 key[k] = 0u;
                 val[k] = (uint32_t)(vsl.rec0 + (int64_t)k * kWave + lane);
+                aux[k] = 0u;
             }
             if (vsl.ok) {  // uniform; on a buffer mismatch nothing is read and nothing is valid
 #pragma unroll
                 for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
                     key[k] = vsl.key(k, lane);
                     vbits |= (uint32_t)((vsl.word(k) >> lane) & 1ull) << k;
+                    aux[k] = vsl.rect(k, lane);
                 }
             }
         } else {
@@ -401,6 +442,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
                 const int64_t e = sort_elem(base, w, k, lane);
                 key[k] = FULL || e < n ? keys_in[e] : 0u;
                 val[k] = FULL || e < n ? vals_in[e] : 0u;
+                if constexpr (AUX) aux[k] = FULL || e < n ? aux_in[e] : 0u;
             }
         }
         auto item_valid = [&](int k) -> bool {
@@ -414,7 +456,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
             const uint32_t d = (key[k] >> shift) & dmask;
             const uint64_t peers = match_digit<RB>(d, valid);
             const uint32_t before = s_wh[w][d];
-            if (valid && (peers & lt) == 0) s_wh[w][d] = before + (uint32_t)__popcll(peers);
+            if (valid && (peers & lt) == 0) s_wh[w][d] = (WH)(before + (uint32_t)__popcll(peers));
             rank[k] = before + (uint32_t)__popcll(peers & lt);
         }
         __syncthreads();
@@ -439,7 +481,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
                 s_goff[dd] -= st;
 #pragma unroll
                 for (int ww = 0; ww < NW; ++ww) {
-                    s_wh[ww][dd] = st;
+                    s_wh[ww][dd] = (WH)st;
                     st += c[q][ww];
                 }
             }
@@ -451,6 +493,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
                 const uint32_t pos = s_wh[w][(key[k] >> shift) & dmask] + rank[k];
                 s_keys[pos] = key[k];
                 s_vals[pos] = val[k];
+                if constexpr (AUX) s_aux[pos] = aux[k];
             }
         }
     };
@@ -467,7 +510,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
         const uint32_t vv = s_vals[j];
         if (!last) keys_out[o] = kk;
         vals_out[o] = vv;
-        if (last && gather_src) gather_out[o] = gather_src[vv];
+        if constexpr (AUX) aux_out[o] = s_aux[j];
         if (last && ranges) {
             if (j == 0 || s_keys[j - 1] != kk) atomicMin(&ranges[kk].x, o);
             if (j == cnt_blk - 1 || s_keys[j + 1] != kk) atomicMax(&ranges[kk].y, o + 1);
@@ -483,33 +526,36 @@ int radix_passes(int bits) { return (bits + kMaxRadixBits - 1) / kMaxRadixBits; 
 // split into radix_passes() digits of at most kMaxRadixBits, as even as
 // possible (17 bits: 9 + 8, not 8 + 8 + 1).  Each pass: per-chunk digit
 // counts, a per-digit scan over the chunks (with the digit totals in
-// `totals`, kMaxRadix entries), and the stable scatter.  gather_* and ranges
-// apply to the last pass (see radix_downsweep_kernel).
+// `totals`, kMaxRadix entries), and the stable scatter.  ranges applies to
+// the last pass (see radix_downsweep_kernel).  With xa and xb a second value
+// per element is carried in them (8-bit digits only), ending in the same
+// buffer half as the values; with vis the first pass reads the elements in
+// place (see VisSrc) and the carried word is the packed tile rectangle.
 hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Count cnt, int bit_lo,
                       int bit_hi, uint32_t *hist, uint32_t *totals, hipStream_t s, bool *result_in_b,
-                      const uint2 *gather_src = nullptr, uint2 *gather_out = nullptr, uint2 *ranges = nullptr,
-                      const VisSrc *vis = nullptr)
+                      uint2 *ranges = nullptr, const VisSrc *vis = nullptr, uint32_t *xa = nullptr,
+                      uint32_t *xb = nullptr)
 {
     const int bits = bit_hi - bit_lo, passes = radix_passes(bits);
-    if (vis && (passes < 2 || bits > 8 * passes)) return hipErrorInvalidValue;  // 8-bit first pass, not the last
+    const bool aux = xa != nullptr;
+    if (vis && (!aux || passes < 2 || bits > 8 * passes)) return hipErrorInvalidValue;  // 8-bit first pass, not the last
+    if (aux && bits > 8 * passes) return hipErrorInvalidValue;
     bool in_b = false;
     int shift = bit_lo;
     for (int p = 0; p < passes; ++p) {
         const int width = (bits - (shift - bit_lo) + (passes - p) - 1) / (passes - p);
-        const uint32_t *kin = in_b ? kb : ka, *vin = in_b ? vb : va;
-        uint32_t *kout = in_b ? ka : kb, *vout = in_b ? va : vb;
+        const uint32_t *kin = in_b ? kb : ka, *vin = in_b ? vb : va, *xin = in_b ? xb : xa;
+        uint32_t *kout = in_b ? ka : kb, *vout = in_b ? va : vb, *xout = in_b ? xa : xb;
         const bool last = p == passes - 1;
-        const uint2 *gs = last ? gather_src : nullptr;
-        uint2 *go = last ? gather_out : nullptr;
         uint2 *rg = last ? ranges : nullptr;
-        if (p == 0 && vis) {  // straight from the visibility bits and depth keys
+        if (p == 0 && vis) {  // straight from the visibility bits, depth keys and tile rectangles
             const int64_t nb = vis->nbc, hs = hist_stride(nb);
             radix_upsweep_kernel<8, true><<<(unsigned)nb, kSortThreads, 0, s>>>(nullptr, cnt, shift, width, hist,
                                                                                  hs, *vis);
             scan_digits_kernel<<<1u << 8, kDigitScanThreads, 0, s>>>(hist, hs, Count{nullptr, nb * kSortTile},
                                                                      totals);
-            radix_downsweep_kernel<8, true><<<(unsigned)nb, kSortThreads, 0, s>>>(
-                nullptr, nullptr, kout, vout, cnt, shift, width, hist, totals, hs, nullptr, nullptr, nullptr, *vis);
+            radix_downsweep_kernel<8, true, false, true><<<(unsigned)nb, kSortThreads, 0, s>>>(
+                nullptr, nullptr, kout, vout, cnt, shift, width, hist, totals, hs, nullptr, xout, nullptr, *vis);
             in_b = !in_b;
             shift += width;
             continue;
@@ -519,21 +565,27 @@ hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Co
         if (width <= 8) {
             radix_upsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, hstride);
             scan_digits_kernel<<<1u << 8, kDigitScanThreads, 0, s>>>(hist, hstride, cnt, totals);
-            if (last)
+            if (aux && last)
+                radix_downsweep_kernel<8, false, true, true><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, xin, xout, rg);
+            else if (aux)
+                radix_downsweep_kernel<8, false, false, true><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, xin, xout, rg);
+            else if (last)
                 radix_downsweep_kernel<8, false, true><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg);
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, nullptr, nullptr, rg);
             else
                 radix_downsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg);
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, nullptr, nullptr, rg);
         } else {
             radix_upsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, hstride);
             scan_digits_kernel<<<1u << 9, kDigitScanThreads, 0, s>>>(hist, hstride, cnt, totals);
             if (last)
                 radix_downsweep_kernel<9, false, true><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg);
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, nullptr, nullptr, rg);
             else
                 radix_downsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, gs, go, rg);
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, nullptr, nullptr, rg);
         }
         in_b = !in_b;
         shift += width;
@@ -572,21 +624,6 @@ __global__ void finalize_counts_kernel(const ProjHeader *ph, BinsHeader *bh, int
 constexpr int kCompactItems = 16;
 constexpr int kCompactTile = kSortThreads * kCompactItems;
 
-// Tile rectangle of a sorted record's pixel box (tile sides 2^lw x 2^lh;
-// boxes are clipped to the image, so the coordinates are not negative).
-struct TileRect {
-    int tx0, ty0, w, h;
-};
-__device__ __forceinline__ TileRect tile_rect(short4 b, int lw, int lh)
-{
-    TileRect r;
-    r.tx0 = b.x >> lw;
-    r.ty0 = b.z >> lh;
-    r.w = (b.y >> lw) - r.tx0 + 1;
-    r.h = (b.w >> lh) - r.ty0 + 1;
-    return r;
-}
-
 // floor(x / d) for 32-bit x and a divisor d >= 2 fixed for the launch, from
 // m = ceil(2^64 / d): x m / 2^64 exceeds x / d by less than 2^-32, which
 // cannot carry it past the next integer.
@@ -606,7 +643,8 @@ __device__ __forceinline__ uint32_t div32(uint32_t x, const Div32 &d) { return d
 // Pair counts of the depth-ordered records: per block of 4096 records (16
 // consecutive ones per thread) into block_sum, and per group of 256 records
 // (one emission block) into group_sum.
-__global__ __launch_bounds__(kSortThreads) void count_pairs_kernel(const BinsHeader *bh, const short4 *sorted_box,
+__global__ __launch_bounds__(kSortThreads) void count_pairs_kernel(const BinsHeader *bh, const uint32_t *sorted_rect,
+                                                                   const uint32_t *sorted_rec, const short4 *bbox,
                                                                    int lw, int lh, uint32_t *block_sum,
                                                                    uint32_t *group_sum)
 {
@@ -618,19 +656,23 @@ __global__ __launch_bounds__(kSortThreads) void count_pairs_kernel(const BinsHea
     const int64_t e0 = base + (int64_t)t * kCompactItems;
     uint32_t cnt = 0;
     if (e0 + kCompactItems <= nvis) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(sorted_box + e0);
+        const uint4 *src = reinterpret_cast<const uint4 *>(sorted_rect + e0);
 #pragma unroll
-        for (int q = 0; q < kCompactItems / 2; ++q) {
-            const uint4 u = src[q];  // two boxes
-            const short4 b0 = __builtin_bit_cast(short4, make_uint2(u.x, u.y));
-            const short4 b1 = __builtin_bit_cast(short4, make_uint2(u.z, u.w));
-            const TileRect r0 = tile_rect(b0, lw, lh), r1 = tile_rect(b1, lw, lh);
-            cnt += (uint32_t)(r0.w * r0.h + r1.w * r1.h);
+        for (int q = 0; q < kCompactItems / 4; ++q) {
+            const uint4 u = src[q];  // four rectangles
+            const uint32_t pr[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const TileRect r = pr[c] != kRectEscape ? unpack_rect(pr[c])
+                                                        : tile_rect(bbox[sorted_rec[e0 + 4 * q + c]], lw, lh);
+                cnt += (uint32_t)(r.w * r.h);
+            }
         }
     } else {
         for (int q = 0; q < kCompactItems; ++q)
             if (e0 + q < nvis) {
-                const TileRect r = tile_rect(sorted_box[e0 + q], lw, lh);
+                const uint32_t pr = sorted_rect[e0 + q];
+                const TileRect r = pr != kRectEscape ? unpack_rect(pr) : tile_rect(bbox[sorted_rec[e0 + q]], lw, lh);
                 cnt += (uint32_t)(r.w * r.h);
             }
     }
@@ -654,7 +696,8 @@ __global__ __launch_bounds__(kSortThreads) void count_pairs_kernel(const BinsHea
 // the step (their start positions are flagged in LDS and read back as one
 // ballot).
 __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, const uint32_t *sorted_rec,
-                                                         const short4 *sorted_box, const ViewDesc *views,
+                                                         const uint32_t *sorted_rect, const short4 *bbox,
+                                                         const ViewDesc *views,
                                                          Div32 n, int lw, int lh, const uint32_t *block_sum,
                                                          const uint32_t *group_sum, uint32_t *pkeys,
                                                          uint32_t *pvals)
@@ -672,7 +715,8 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, c
     uint32_t cnt = 0;
     if (t < cntb) {
         const uint32_t rec = sorted_rec[j0 + t];
-        const TileRect r = tile_rect(sorted_box[j0 + t], lw, lh);
+        const uint32_t pr = sorted_rect[j0 + t];
+        const TileRect r = pr != kRectEscape ? unpack_rect(pr) : tile_rect(bbox[rec], lw, lh);
         const ViewDesc &V = views[div32(rec, n)];
         cnt = (uint32_t)(r.w * r.h);
         s_rec[t] = rec;
@@ -799,16 +843,19 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     uint32_t *hist = (uint32_t *)(wb + L.hist), *totals = (uint32_t *)(wb + L.totals);
     uint32_t *tkeys_a = (uint32_t *)(wb + L.tkeys_a), *tvals_tmp = (uint32_t *)(wb + L.tvals_a);
     uint32_t *tkeys_b = (uint32_t *)(wb + L.tkeys_b);
-    uint2 *sorted_box = (uint2 *)(wb + L.sorted_box);
+    uint32_t *rect_a = (uint32_t *)(wb + L.rect_a), *rect_b = (uint32_t *)(wb + L.rect_b);
     const int64_t R = n * n_views;
+    int lw = 0, lh = 0;  // tile sides are powers of two
+    while ((1 << lw) < tile_w) ++lw;
+    while ((1 << lh) < tile_h) ++lh;
     hipError_t e;
 
     finalize_counts_kernel<<<1, 64, 0, s>>>(P.hdr, B.hdr, n, n_views, tile_w, tile_h, cap, (uint32_t)n_tiles,
                                             overflow_out);
 
     // 1. sort the visible records by depth bits, stably in record order: the
-    // first pass reads the visibility bits and depth keys in place, the last
-    // also writes each sorted record's pixel box contiguously
+    // first pass reads the visibility bits, depth keys and packed tile
+    // rectangles in place; each record's rectangle travels with it
     const Count vis_cnt{&B.hdr->n_vis, R};
     bool depth_in_b = false;
     if (R > 0) {
@@ -820,11 +867,13 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
         vs.vstride = visbits_stride(n);
         vs.nbv = ceil_div(n, kSortTile);
         vs.nbc = n_views * vs.nbv;
-        e = radix_sort(keys_a, vals_a, keys_b, vals_b, vis_cnt, 0, 32, hist, totals, s, &depth_in_b,
-                       (const uint2 *)P.bbox, sorted_box, nullptr, &vs);
+        vs.rect = P.rect;
+        e = radix_sort(keys_a, vals_a, keys_b, vals_b, vis_cnt, 0, 32, hist, totals, s, &depth_in_b, nullptr, &vs,
+                       rect_a, rect_b);
         if (e != hipSuccess) return e;
     }
     const uint32_t *sorted_rec = depth_in_b ? vals_b : vals_a;
+    const uint32_t *sorted_rect = depth_in_b ? rect_b : rect_a;
 
     // 2. pair offsets in depth order, emit (tile, record) pairs
     // at least one pass, whose scatter records the tile ranges (one tile: a 1-bit pass of zero keys)
@@ -834,14 +883,12 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     uint32_t *other_vals = odd ? B.pair_rec : pvals_b;
     if (R > 0 && cap > 0) {
         const int64_t nb = ceil_div(R, kCompactTile);
-        int lw = 0, lh = 0;  // tile sides are powers of two
-        while ((1 << lw) < tile_w) ++lw;
-        while ((1 << lh) < tile_h) ++lh;
-        count_pairs_kernel<<<(unsigned)nb, kSortThreads, 0, s>>>(B.hdr, (const short4 *)sorted_box, lw, lh,
-                                                                 block_sum, group_sum);
+        count_pairs_kernel<<<(unsigned)nb, kSortThreads, 0, s>>>(B.hdr, sorted_rect, sorted_rec,
+                                                                 (const short4 *)P.bbox, lw, lh, block_sum,
+                                                                 group_sum);
         scan_partials_kernel<<<1, 1024, 0, s>>>(block_sum, nb, &B.hdr->n_vis, kCompactTile);
-        emit_pairs_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(B.hdr, sorted_rec, (const short4 *)sorted_box,
-                                                                     P.views, make_div32((uint32_t)n), lw, lh, block_sum,
+        emit_pairs_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(B.hdr, sorted_rec, sorted_rect,
+                                                                     (const short4 *)P.bbox, P.views, make_div32((uint32_t)n), lw, lh, block_sum,
                                                                      group_sum, pkeys_a, emit_vals);
         // 3. stable sort by global tile id; its last pass records the tile ranges
         if (n_tiles > 0)
@@ -849,7 +896,7 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
         bool pairs_in_b = false;
         const Count pair_cnt{&B.hdr->n_pairs, cap};
         e = radix_sort(pkeys_a, emit_vals, pkeys_b, other_vals, pair_cnt, 0, tile_bits, hist, totals, s,
-                       &pairs_in_b, nullptr, nullptr, B.tile_range);
+                       &pairs_in_b, B.tile_range);
         if (e != hipSuccess) return e;
     } else {
         fill_u32_kernel<<<(unsigned)ceil_div(2 * n_tiles, 256), 256, 0, s>>>((uint32_t *)B.tile_range,

@@ -157,6 +157,36 @@ def test_binning_bit_exact_wide_tile_keys(oracle, width):
     assert np.all(rng[~nonempty, 0] == rng[~nonempty, 1])
 
 
+def test_binning_bit_exact_unpacked_rectangles(oracle):
+    """The depth sort carries each record's tile rectangle packed in 32 bits
+    (columns and rows up to 1023, at most 64 tiles across); others are taken
+    from the pixel box.  A view 8320 pixels wide with 8x8 tiles (1040 tile
+    columns) and splats up to a few hundred pixels across: records past
+    column 1023 and records wider than 64 tiles both occur, and the whole
+    pair list matches the oracle's."""
+    s = tiny_scene(3000, 29, lo=(-18.0, -0.6, 3.0), hi=(18.0, 0.6, 8.0), log_scale=(np.log(0.02), np.log(1.0)))
+    W, H = 8320, 512
+    cam = scenes.camera(W, H, f=2000.0)
+    out = gpu_render(s, [cam], cfg(8, 8))
+    rast = out["rast"]
+    b = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in rast.bins_arrays().items()}
+    rec = {k: v.cpu().numpy() for k, v in rast.records().items()}
+    p = oracle.project(s, cam)
+    vis = p["valid"] == 1
+    bx = p["bbox"][vis].astype(np.int64)
+    tx0, w = bx[:, 0] >> 3, (bx[:, 1] >> 3) - (bx[:, 0] >> 3) + 1
+    assert np.sum(tx0 + w > 1024) > 20 and np.sum(w > 64) > 20 and np.sum((tx0 + w <= 1024) & (w <= 64)) > 500
+    start, ids = oracle.bin_pairs(p["valid"], p["bbox"], p["depth_key"], W, H, 8, 8)
+    nt = (W // 8) * (H // 8)
+    assert start.size - 1 == nt and ids.size == int(rec["counts"][1])
+    np.testing.assert_array_equal(b["pair_rec"][:ids.size].astype(np.int64), ids)
+    rng = b["tile_range"][:nt].astype(np.int64)
+    nonempty = start[1:] > start[:-1]
+    np.testing.assert_array_equal(rng[nonempty, 0], start[:-1][nonempty])
+    np.testing.assert_array_equal(rng[nonempty, 1], start[1:][nonempty])
+    assert np.all(rng[~nonempty, 0] == rng[~nonempty, 1])
+
+
 # ---------------------------------------------------------------- forward
 
 def test_forward_config0(oracle):
