@@ -146,8 +146,8 @@ inline int64_t hist_stride(int64_t nblocks) { return (nblocks + 3) / 4 * 4; }
 
 struct WorkLayout {
     // bin/sort phase
-    size_t keys_a, vals_a, keys_b, vals_b, block_sum, group_sum, pkeys_a, pkeys_b, pvals_b, hist, totals,
-        tkeys_a, tvals_a, tkeys_b, rect_a, rect_b, sort_total;
+    size_t keys_a, dvals_a, keys_b, dvals_b, block_sum, group_sum, pkeys_a, pkeys_b, pvals_b, hist, totals,
+        tkeys_a, tvals_a, tkeys_b, sort_total;
     size_t total;
     int64_t hist_blocks;  // max sort blocks of any sort
 };
@@ -162,10 +162,11 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     L.hist_blocks = ceil_div(maxn > 0 ? maxn : 1, kSortTile);
     if (nbc > L.hist_blocks) L.hist_blocks = nbc;
     size_t hist_n = (size_t)hist_stride(L.hist_blocks) * kMaxRadix;
+    // depth sort: keys and (record, packed tile rectangle) values, ping-pong
     L.keys_a = o;   o = align_up(o + 4 * R);
-    L.vals_a = o;   o = align_up(o + 4 * R);
+    L.dvals_a = o;  o = align_up(o + 8 * R);
     L.keys_b = o;   o = align_up(o + 4 * R);
-    L.vals_b = o;   o = align_up(o + 4 * R);
+    L.dvals_b = o;  o = align_up(o + 8 * R);
     // output offsets of blocks of 4096 records (pair counts) and the pair
     // counts of their groups of 256 records (pair emission)
     const int64_t nbs = ceil_div((int64_t)R > 0 ? (int64_t)R : 1, 4096);
@@ -179,9 +180,6 @@ inline WorkLayout work_layout(int64_t n, int32_t n_views, int64_t cap, int64_t n
     L.tkeys_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
     L.tvals_a = o;  o = align_up(o + 4 * (size_t)n_tiles);
     L.tkeys_b = o;  o = align_up(o + 4 * (size_t)n_tiles);
-    // packed tile rectangles carried through the depth sort (ping-pong)
-    L.rect_a = o;   o = align_up(o + 4 * R);
-    L.rect_b = o;   o = align_up(o + 4 * R);
     L.sort_total = o;
     L.total = L.sort_total;
     return L;

@@ -354,9 +354,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
 // The output offset of digit d of this chunk is the digit's base (the
 // exclusive scan of the digit totals) plus the chunk's entry of the
 // per-digit scanned histogram.  The last pass writes no keys (they are not
-// needed afterwards).  AUX: a second 32-bit value per element is carried
-// beside the first (aux_in to aux_out; in the VIS pass, the packed tile
-// rectangle of the record's pixel box).  In the last pass, if ranges is set
+// needed afterwards).  AUX: the values are pairs (record, packed tile
+// rectangle), moved as one 8-byte word; the VIS pass builds them from the
+// record index and the preprocess's rectangles.  In the last pass, if ranges is set
 // (a sort by the full key, ranges[] holding (~0, 0) before), each key's
 // output range [start, end) is recorded in ranges[key]: a block's equal keys
 // are contiguous in its LDS-sorted order and in the output, and the blocks'
@@ -365,18 +365,20 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
 // no carried word it is held to 128 VGPRs for a fourth wavefront per SIMD
 // (measured faster there, not in the other passes; 9-bit passes are held to
 // three by their LDS).
+template <bool AUX>
+using SortVal = std::conditional_t<AUX, uint2, uint32_t>;
+
 template <int RB, bool VIS = false, bool LAST = false, bool AUX = false>
 __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LAST && RB == 8 && !AUX ? 4 : 1))) void radix_downsweep_kernel(
-    const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
-    uint32_t *__restrict__ vals_out, Count cnt, int shift, int width, const uint32_t *hist,
-    const uint32_t *totals, int64_t hstride, const uint32_t *__restrict__ aux_in, uint32_t *__restrict__ aux_out,
-    uint2 *ranges, VisSrc vs = {})
+    const uint32_t *__restrict__ keys_in, const SortVal<AUX> *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
+    SortVal<AUX> *__restrict__ vals_out, Count cnt, int shift, int width, const uint32_t *hist,
+    const uint32_t *totals, int64_t hstride, uint2 *ranges, VisSrc vs = {})
 {
+    using VT = SortVal<AUX>;
     constexpr bool last = LAST;
     constexpr int NW = kSortThreads / kWave, RADIX = 1 << RB, DPT = RADIX / kSortThreads;
     __shared__ uint32_t s_keys[kSortTile];
-    __shared__ uint32_t s_vals[kSortTile];
-    __shared__ uint32_t s_aux[AUX ? kSortTile : 1];
+    __shared__ VT s_vals[kSortTile];
     // per-wave digit counts, then per-wave offsets (below 4096); 16-bit where
     // a word is carried, so that three workgroups fit in a CU's LDS
     using WH = std::conditional_t<AUX, uint16_t, uint32_t>;
@@ -416,7 +418,8 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
     const bool full = !VIS && base + kSortTile <= n;  // uniform across the block
     auto sort_chunk = [&](auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
-        uint32_t key[kSortItems], val[kSortItems], rank[kSortItems], aux[AUX ? kSortItems : 1];
+        uint32_t key[kSortItems], rank[kSortItems];
+        VT val[kSortItems];
         uint32_t vbits = 0;  // VIS: bit k set where item k is valid
         const uint64_t lt = lanemask_lt();
         if constexpr (VIS) {
@@ -425,15 +428,14 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
 #pragma unroll
             for (int k = 0; k < kSortItems; ++k) {
                 key[k] = 0u;
-                val[k] = (uint32_t)(vsl.rec0 + (int64_t)k * kWave + lane);
-                aux[k] = 0u;
+                val[k] = make_uint2((uint32_t)(vsl.rec0 + (int64_t)k * kWave + lane), 0u);
             }
             if (vsl.ok) {  // uniform; on a buffer mismatch nothing is read and nothing is valid
 #pragma unroll
                 for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
                     key[k] = vsl.key(k, lane);
                     vbits |= (uint32_t)((vsl.word(k) >> lane) & 1ull) << k;
-                    aux[k] = vsl.rect(k, lane);
+                    val[k].y = vsl.rect(k, lane);
                 }
             }
         } else {
@@ -441,8 +443,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
             for (int k = 0; k < kSortItems; ++k) {  // all loads in flight before the ranking
                 const int64_t e = sort_elem(base, w, k, lane);
                 key[k] = FULL || e < n ? keys_in[e] : 0u;
-                val[k] = FULL || e < n ? vals_in[e] : 0u;
-                if constexpr (AUX) aux[k] = FULL || e < n ? aux_in[e] : 0u;
+                val[k] = FULL || e < n ? vals_in[e] : VT{};
             }
         }
         auto item_valid = [&](int k) -> bool {
@@ -493,7 +494,6 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
                 const uint32_t pos = s_wh[w][(key[k] >> shift) & dmask] + rank[k];
                 s_keys[pos] = key[k];
                 s_vals[pos] = val[k];
-                if constexpr (AUX) s_aux[pos] = aux[k];
             }
         }
     };
@@ -507,10 +507,8 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
         const uint32_t kk = s_keys[j];
         const uint32_t d = (kk >> shift) & dmask;
         const uint32_t o = s_goff[d] + (uint32_t)j;
-        const uint32_t vv = s_vals[j];
         if (!last) keys_out[o] = kk;
-        vals_out[o] = vv;
-        if constexpr (AUX) aux_out[o] = s_aux[j];
+        vals_out[o] = s_vals[j];
         if (last && ranges) {
             if (j == 0 || s_keys[j - 1] != kk) atomicMin(&ranges[kk].x, o);
             if (j == cnt_blk - 1 || s_keys[j + 1] != kk) atomicMax(&ranges[kk].y, o + 1);
@@ -527,65 +525,62 @@ int radix_passes(int bits) { return (bits + kMaxRadixBits - 1) / kMaxRadixBits; 
 // possible (17 bits: 9 + 8, not 8 + 8 + 1).  Each pass: per-chunk digit
 // counts, a per-digit scan over the chunks (with the digit totals in
 // `totals`, kMaxRadix entries), and the stable scatter.  ranges applies to
-// the last pass (see radix_downsweep_kernel).  With xa and xb a second value
-// per element is carried in them (8-bit digits only), ending in the same
-// buffer half as the values; with vis the first pass reads the elements in
-// place (see VisSrc) and the carried word is the packed tile rectangle.
-hipError_t radix_sort(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, Count cnt, int bit_lo,
-                      int bit_hi, uint32_t *hist, uint32_t *totals, hipStream_t s, bool *result_in_b,
-                      uint2 *ranges = nullptr, const VisSrc *vis = nullptr, uint32_t *xa = nullptr,
-                      uint32_t *xb = nullptr)
+// the last pass (see radix_downsweep_kernel).  Values of type uint2 are
+// (record, packed tile rectangle) pairs and take 8-bit digits only; with vis
+// the first pass reads the elements in place (see VisSrc).
+template <typename VT>
+hipError_t radix_sort(uint32_t *ka, VT *va, uint32_t *kb, VT *vb, Count cnt, int bit_lo, int bit_hi,
+                      uint32_t *hist, uint32_t *totals, hipStream_t s, bool *result_in_b, uint2 *ranges = nullptr,
+                      const VisSrc *vis = nullptr)
 {
+    constexpr bool aux = std::is_same_v<VT, uint2>;
     const int bits = bit_hi - bit_lo, passes = radix_passes(bits);
-    const bool aux = xa != nullptr;
     if (vis && (!aux || passes < 2 || bits > 8 * passes)) return hipErrorInvalidValue;  // 8-bit first pass, not the last
     if (aux && bits > 8 * passes) return hipErrorInvalidValue;
     bool in_b = false;
     int shift = bit_lo;
     for (int p = 0; p < passes; ++p) {
         const int width = (bits - (shift - bit_lo) + (passes - p) - 1) / (passes - p);
-        const uint32_t *kin = in_b ? kb : ka, *vin = in_b ? vb : va, *xin = in_b ? xb : xa;
-        uint32_t *kout = in_b ? ka : kb, *vout = in_b ? va : vb, *xout = in_b ? xa : xb;
+        const uint32_t *kin = in_b ? kb : ka;
+        const VT *vin = in_b ? vb : va;
+        uint32_t *kout = in_b ? ka : kb;
+        VT *vout = in_b ? va : vb;
         const bool last = p == passes - 1;
         uint2 *rg = last ? ranges : nullptr;
-        if (p == 0 && vis) {  // straight from the visibility bits, depth keys and tile rectangles
-            const int64_t nb = vis->nbc, hs = hist_stride(nb);
-            radix_upsweep_kernel<8, true><<<(unsigned)nb, kSortThreads, 0, s>>>(nullptr, cnt, shift, width, hist,
-                                                                                 hs, *vis);
-            scan_digits_kernel<<<1u << 8, kDigitScanThreads, 0, s>>>(hist, hs, Count{nullptr, nb * kSortTile},
-                                                                     totals);
-            radix_downsweep_kernel<8, true, false, true><<<(unsigned)nb, kSortThreads, 0, s>>>(
-                nullptr, nullptr, kout, vout, cnt, shift, width, hist, totals, hs, nullptr, xout, nullptr, *vis);
-            in_b = !in_b;
-            shift += width;
-            continue;
+        if constexpr (aux) {
+            if (p == 0 && vis) {  // straight from the visibility bits, depth keys and tile rectangles
+                const int64_t nb = vis->nbc, hs = hist_stride(nb);
+                radix_upsweep_kernel<8, true><<<(unsigned)nb, kSortThreads, 0, s>>>(nullptr, cnt, shift, width,
+                                                                                     hist, hs, *vis);
+                scan_digits_kernel<<<1u << 8, kDigitScanThreads, 0, s>>>(hist, hs, Count{nullptr, nb * kSortTile},
+                                                                         totals);
+                radix_downsweep_kernel<8, true, false, true><<<(unsigned)nb, kSortThreads, 0, s>>>(
+                    nullptr, nullptr, kout, vout, cnt, shift, width, hist, totals, hs, nullptr, *vis);
+                in_b = !in_b;
+                shift += width;
+                continue;
+            }
         }
         const int64_t nblocks = ceil_div(cnt.host > 0 ? cnt.host : 1, kSortTile);
         const int64_t hstride = hist_stride(nblocks);  // histogram rows start on 16 bytes
         if (width <= 8) {
             radix_upsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, hstride);
             scan_digits_kernel<<<1u << 8, kDigitScanThreads, 0, s>>>(hist, hstride, cnt, totals);
-            if (aux && last)
-                radix_downsweep_kernel<8, false, true, true><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, xin, xout, rg);
-            else if (aux)
-                radix_downsweep_kernel<8, false, false, true><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, xin, xout, rg);
-            else if (last)
-                radix_downsweep_kernel<8, false, true><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, nullptr, nullptr, rg);
+            if (last)
+                radix_downsweep_kernel<8, false, true, aux><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, rg);
             else
-                radix_downsweep_kernel<8><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, nullptr, nullptr, rg);
-        } else {
+                radix_downsweep_kernel<8, false, false, aux><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, rg);
+        } else if constexpr (!aux) {
             radix_upsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(kin, cnt, shift, width, hist, hstride);
             scan_digits_kernel<<<1u << 9, kDigitScanThreads, 0, s>>>(hist, hstride, cnt, totals);
             if (last)
                 radix_downsweep_kernel<9, false, true><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, nullptr, nullptr, rg);
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, rg);
             else
                 radix_downsweep_kernel<9><<<(unsigned)nblocks, kSortThreads, 0, s>>>(
-                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, nullptr, nullptr, rg);
+                    kin, vin, kout, vout, cnt, shift, width, hist, totals, hstride, rg);
         }
         in_b = !in_b;
         shift += width;
@@ -643,10 +638,9 @@ __device__ __forceinline__ uint32_t div32(uint32_t x, const Div32 &d) { return d
 // Pair counts of the depth-ordered records: per block of 4096 records (16
 // consecutive ones per thread) into block_sum, and per group of 256 records
 // (one emission block) into group_sum.
-__global__ __launch_bounds__(kSortThreads) void count_pairs_kernel(const BinsHeader *bh, const uint32_t *sorted_rect,
-                                                                   const uint32_t *sorted_rec, const short4 *bbox,
-                                                                   int lw, int lh, uint32_t *block_sum,
-                                                                   uint32_t *group_sum)
+__global__ __launch_bounds__(kSortThreads) void count_pairs_kernel(const BinsHeader *bh, const uint2 *sorted,
+                                                                   const short4 *bbox, int lw, int lh,
+                                                                   uint32_t *block_sum, uint32_t *group_sum)
 {
     __shared__ uint32_t s_tmp[kSortThreads / kWave + 1];
     const int64_t nvis = bh->overflow ? 0 : (int64_t)bh->n_vis;
@@ -656,23 +650,39 @@ __global__ __launch_bounds__(kSortThreads) void count_pairs_kernel(const BinsHea
     const int64_t e0 = base + (int64_t)t * kCompactItems;
     uint32_t cnt = 0;
     if (e0 + kCompactItems <= nvis) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(sorted_rect + e0);
+        // the packed rectangles first, with no branch between the loads; a
+        // thread with an escaped rectangle (rare) then counts that one again
+        // from its pixel box
+        const uint4 *src = reinterpret_cast<const uint4 *>(sorted + e0);
+        uint4 u[kCompactItems / 2];  // two (record, rectangle) pairs each
 #pragma unroll
-        for (int q = 0; q < kCompactItems / 4; ++q) {
-            const uint4 u = src[q];  // four rectangles
-            const uint32_t pr[4] = {u.x, u.y, u.z, u.w};
+        for (int q = 0; q < kCompactItems / 2; ++q) u[q] = src[q];
+        bool esc = false;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const TileRect r = pr[c] != kRectEscape ? unpack_rect(pr[c])
-                                                        : tile_rect(bbox[sorted_rec[e0 + 4 * q + c]], lw, lh);
-                cnt += (uint32_t)(r.w * r.h);
+        for (int q = 0; q < kCompactItems / 2; ++q) {
+            const TileRect r0 = unpack_rect(u[q].y), r1 = unpack_rect(u[q].w);
+            cnt += (u[q].y != kRectEscape ? (uint32_t)(r0.w * r0.h) : 0u) +
+                   (u[q].w != kRectEscape ? (uint32_t)(r1.w * r1.h) : 0u);
+            esc |= u[q].y == kRectEscape || u[q].w == kRectEscape;
+        }
+        if (esc) {
+#pragma unroll
+            for (int q = 0; q < kCompactItems / 2; ++q) {
+                if (u[q].y == kRectEscape) {
+                    const TileRect r = tile_rect(bbox[u[q].x], lw, lh);
+                    cnt += (uint32_t)(r.w * r.h);
+                }
+                if (u[q].w == kRectEscape) {
+                    const TileRect r = tile_rect(bbox[u[q].z], lw, lh);
+                    cnt += (uint32_t)(r.w * r.h);
+                }
             }
         }
     } else {
         for (int q = 0; q < kCompactItems; ++q)
             if (e0 + q < nvis) {
-                const uint32_t pr = sorted_rect[e0 + q];
-                const TileRect r = pr != kRectEscape ? unpack_rect(pr) : tile_rect(bbox[sorted_rec[e0 + q]], lw, lh);
+                const uint2 u = sorted[e0 + q];
+                const TileRect r = u.y != kRectEscape ? unpack_rect(u.y) : tile_rect(bbox[u.x], lw, lh);
                 cnt += (uint32_t)(r.w * r.h);
             }
     }
@@ -695,9 +705,8 @@ __global__ __launch_bounds__(kSortThreads) void count_pairs_kernel(const BinsHea
 // over), plus the number of records that start at or before the pair within
 // the step (their start positions are flagged in LDS and read back as one
 // ballot).
-__global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, const uint32_t *sorted_rec,
-                                                         const uint32_t *sorted_rect, const short4 *bbox,
-                                                         const ViewDesc *views,
+__global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, const uint2 *sorted,
+                                                         const short4 *bbox, const ViewDesc *views,
                                                          Div32 n, int lw, int lh, const uint32_t *block_sum,
                                                          const uint32_t *group_sum, uint32_t *pkeys,
                                                          uint32_t *pvals)
@@ -714,9 +723,9 @@ __global__ __launch_bounds__(256) void emit_pairs_kernel(const BinsHeader *bh, c
     const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
     uint32_t cnt = 0;
     if (t < cntb) {
-        const uint32_t rec = sorted_rec[j0 + t];
-        const uint32_t pr = sorted_rect[j0 + t];
-        const TileRect r = pr != kRectEscape ? unpack_rect(pr) : tile_rect(bbox[rec], lw, lh);
+        const uint2 u = sorted[j0 + t];
+        const uint32_t rec = u.x;
+        const TileRect r = u.y != kRectEscape ? unpack_rect(u.y) : tile_rect(bbox[rec], lw, lh);
         const ViewDesc &V = views[div32(rec, n)];
         cnt = (uint32_t)(r.w * r.h);
         s_rec[t] = rec;
@@ -835,15 +844,14 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
 {
     const WorkLayout L = work_layout(n, n_views, cap, n_tiles);
     char *wb = (char *)work;
-    uint32_t *keys_a = (uint32_t *)(wb + L.keys_a), *vals_a = (uint32_t *)(wb + L.vals_a);
-    uint32_t *keys_b = (uint32_t *)(wb + L.keys_b), *vals_b = (uint32_t *)(wb + L.vals_b);
+    uint32_t *keys_a = (uint32_t *)(wb + L.keys_a), *keys_b = (uint32_t *)(wb + L.keys_b);
+    uint2 *dvals_a = (uint2 *)(wb + L.dvals_a), *dvals_b = (uint2 *)(wb + L.dvals_b);
     uint32_t *block_sum = (uint32_t *)(wb + L.block_sum), *group_sum = (uint32_t *)(wb + L.group_sum);
     uint32_t *pkeys_a = (uint32_t *)(wb + L.pkeys_a), *pkeys_b = (uint32_t *)(wb + L.pkeys_b);
     uint32_t *pvals_b = (uint32_t *)(wb + L.pvals_b);
     uint32_t *hist = (uint32_t *)(wb + L.hist), *totals = (uint32_t *)(wb + L.totals);
     uint32_t *tkeys_a = (uint32_t *)(wb + L.tkeys_a), *tvals_tmp = (uint32_t *)(wb + L.tvals_a);
     uint32_t *tkeys_b = (uint32_t *)(wb + L.tkeys_b);
-    uint32_t *rect_a = (uint32_t *)(wb + L.rect_a), *rect_b = (uint32_t *)(wb + L.rect_b);
     const int64_t R = n * n_views;
     int lw = 0, lh = 0;  // tile sides are powers of two
     while ((1 << lw) < tile_w) ++lw;
@@ -868,12 +876,11 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
         vs.nbv = ceil_div(n, kSortTile);
         vs.nbc = n_views * vs.nbv;
         vs.rect = P.rect;
-        e = radix_sort(keys_a, vals_a, keys_b, vals_b, vis_cnt, 0, 32, hist, totals, s, &depth_in_b, nullptr, &vs,
-                       rect_a, rect_b);
+        e = radix_sort(keys_a, dvals_a, keys_b, dvals_b, vis_cnt, 0, 32, hist, totals, s, &depth_in_b, nullptr,
+                       &vs);
         if (e != hipSuccess) return e;
     }
-    const uint32_t *sorted_rec = depth_in_b ? vals_b : vals_a;
-    const uint32_t *sorted_rect = depth_in_b ? rect_b : rect_a;
+    const uint2 *sorted = depth_in_b ? dvals_b : dvals_a;  // (record, packed tile rectangle) in depth order
 
     // 2. pair offsets in depth order, emit (tile, record) pairs
     // at least one pass, whose scatter records the tile ranges (one tile: a 1-bit pass of zero keys)
@@ -883,11 +890,11 @@ hipError_t launch_bin_sort(ProjPtrs P, BinsPtrs B, void *work, int64_t n, int32_
     uint32_t *other_vals = odd ? B.pair_rec : pvals_b;
     if (R > 0 && cap > 0) {
         const int64_t nb = ceil_div(R, kCompactTile);
-        count_pairs_kernel<<<(unsigned)nb, kSortThreads, 0, s>>>(B.hdr, sorted_rect, sorted_rec,
+        count_pairs_kernel<<<(unsigned)nb, kSortThreads, 0, s>>>(B.hdr, sorted,
                                                                  (const short4 *)P.bbox, lw, lh, block_sum,
                                                                  group_sum);
         scan_partials_kernel<<<1, 1024, 0, s>>>(block_sum, nb, &B.hdr->n_vis, kCompactTile);
-        emit_pairs_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(B.hdr, sorted_rec, sorted_rect,
+        emit_pairs_kernel<<<(unsigned)ceil_div(R, 256), 256, 0, s>>>(B.hdr, sorted,
                                                                      (const short4 *)P.bbox, P.views, make_div32((uint32_t)n), lw, lh, block_sum,
                                                                      group_sum, pkeys_a, emit_vals);
         // 3. stable sort by global tile id; its last pass records the tile ranges
