@@ -1,13 +1,14 @@
 // Tile binning and (view, tile, depth, id) ordering.
 //
-// Sec. 3.2 composites the primitives overlapping a pixel "after sorting by
-// depth".  Instead of one wide radix sort of (tile | depth) keys over all
-// pairs, the order is built in two narrow stable sorts:
+// Sec. 3.2 composites the primitives that overlap a pixel in depth order.
+// Instead of one wide radix sort of (tile | depth) keys over all pairs, the
+// order is built in two narrow stable sorts:
 //   1. radix-sort the visible (view, splat) records by the fp32 bits of
-//      their depth (32 bits; the first pass reads the visibility bits and
-//      depth keys of all records in place, the others the P visible ones);
-//      stability keeps equal depths in record order, i.e. by splat index
-//      within a view;
+//      their depth (32 bits; the first pass reads the visibility bits, depth
+//      keys and packed tile rectangles of all records in place, the others
+//      the P visible ones; each record's rectangle travels with it, so the
+//      emission below reads it in depth order without a gather); stability
+//      keeps equal depths in record order, i.e. by splat index within a view;
 //   2. emit one (global tile id, record) pair per overlapped tile, walking
 //      the records in depth order, and radix-sort the pairs by tile id only
 //      (ceil(log2 tiles) bits, over K pairs); stability keeps the depth
