@@ -412,7 +412,9 @@ dbs_status dbs_projected_layout(void *projected, int64_t n, int32_t n_views, voi
  *   sgrad    [R] 64-byte accumulator line per record: float dL/dmu' (2),
  *            dL/dA00, dL/dA01, dL/dA11, dL/do, dL/db, dL/dcolour (3), 6 unused
  * Between a dbs_project_bwd and the next dbs_raster_bwd, gradmask and sgrad
- * are all zero.  Any output pointer may be NULL. */
+ * are all zero.  The preprocess also keeps, for dbs_bin_sort, each record's
+ * tile rectangle packed in 32 bits (not exposed).  Any output pointer may be
+ * NULL. */
 dbs_status dbs_projected_state(void *projected, int64_t n, int32_t n_views, void **visbits, void **gradmask,
                                void **sgrad);
 
