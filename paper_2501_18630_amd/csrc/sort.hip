@@ -364,13 +364,14 @@ __global__ __launch_bounds__(kSortThreads) void radix_upsweep_kernel(const uint3
 // pieces of a key's range are merged with atomic min / max.
 // LAST: the sort's last pass (values only; ranges).  With 8-bit digits and
 // no carried word it is held to 128 VGPRs for a fourth wavefront per SIMD
-// (measured faster there, not in the other passes; 9-bit passes are held to
-// three by their LDS).
+// (measured faster there, not in the other 8-bit passes); 9-bit passes are
+// held to 128 VGPRs with a 16-bit digit table for the same (the two passes
+// of 18-bit tile keys over 346 M pairs 1929 + 1519 -> 1844 + 1493 us).
 template <bool AUX>
 using SortVal = std::conditional_t<AUX, uint2, uint32_t>;
 
 template <int RB, bool VIS = false, bool LAST = false, bool AUX = false>
-__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LAST && RB == 8 && !AUX ? 4 : 1))) void radix_downsweep_kernel(
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu((LAST && RB == 8 && !AUX) || RB == 9 ? 4 : 1))) void radix_downsweep_kernel(
     const uint32_t *__restrict__ keys_in, const SortVal<AUX> *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     SortVal<AUX> *__restrict__ vals_out, Count cnt, int shift, int width, const uint32_t *hist,
     const uint32_t *totals, int64_t hstride, uint2 *ranges, VisSrc vs = {})
@@ -381,8 +382,9 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LA
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ VT s_vals[kSortTile];
     // per-wave digit counts, then per-wave offsets (below 4096); 16-bit where
-    // a word is carried, so that three workgroups fit in a CU's LDS
-    using WH = std::conditional_t<AUX, uint16_t, uint32_t>;
+    // a word is carried (three workgroups then fit in a CU's LDS) and with
+    // 9-bit digits (four)
+    using WH = std::conditional_t<AUX || RB == 9, uint16_t, uint32_t>;
     __shared__ WH s_wh[NW][RADIX];
     __shared__ uint32_t s_goff[RADIX];
     __shared__ uint32_t s_tmp[NW + 1];
